@@ -1,0 +1,202 @@
+/*
+ * mih.h -- exact k-nearest-neighbour search in Hamming space by multi-index
+ * hashing, on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 1.1 of Norouzi, Punjani, Fleet, "Fast Exact Search in
+ * Hamming Space with Multi-Index Hashing"): given a database of n binary codes
+ * h_0 .. h_{n-1} of q bits and a query g, return the k codes nearest to g in
+ * Hamming distance.  The paper accepts any choice among codes at equal
+ * distance; this library fixes the order to ascending (distance, id), so the
+ * result is unique and every entry point returns the same bits.
+ *
+ * Data layout shared by all calls:
+ *   - a code of `bits` bits (64, 128, 192 or 256) is bits/64 uint64 words;
+ *     bit p of the code is bit (p mod 64) of word floor(p / 64);
+ *   - an array of codes is row-major [count][bits/64], 8-byte aligned;
+ *   - ids are 0-based row numbers of the database array, as uint32
+ *     (so n <= 2^32 - 2, as in Section 6 where ids take 4 bytes);
+ *   - results of query i occupy entries [off_i, off_i + k_i) of out_ids and
+ *     out_dists, with off_i = k_0 + ... + k_{i-1}; entry off_i + r is the
+ *     (r+1)-th nearest code.  When fewer than k_i codes exist the remaining
+ *     entries hold MIH_SENTINEL in both arrays.
+ *
+ * Pointers named device* are HIP device pointers (for example the data_ptr()
+ * of a PyTorch tensor on the GPU); host* pointers are ordinary host memory.
+ * `stream` is a hipStream_t (NULL for the default stream).  Every call below
+ * is blocking: it returns after its work on `stream` has completed.
+ *
+ * Errors: every call returns a status and never aborts.  Argument errors are
+ * detected before any device work or output write (MIH_ERR_INVALID).  Device
+ * failures (launch or runtime errors) return MIH_ERR_DEVICE; exhausted device
+ * memory returns MIH_ERR_NOMEM.  Internal buffer overflows are resolved
+ * inside the library by an exact re-run and never surface.
+ */
+#ifndef MIH_H
+#define MIH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mih_status {
+    MIH_OK = 0,
+    MIH_ERR_INVALID = 1,      /* bad argument: nothing was written            */
+    MIH_ERR_NOMEM = 2,        /* device memory exhausted                       */
+    MIH_ERR_DEVICE = 3,       /* HIP runtime or kernel failure                 */
+    MIH_ERR_UNSUPPORTED = 4,  /* valid request outside this build's limits     */
+    MIH_ERR_CAPACITY = 5      /* server: no free query slot or buffer memory   */
+} mih_status;
+
+#define MIH_SENTINEL 0xFFFFFFFFu
+#define MIH_K_MAX 4096u        /* largest k per query                          */
+#define MIH_M_MAX 64u          /* largest number of substrings                 */
+#define MIH_SUBSTRING_MAX 32u  /* longest substring (direct tables, Section 6) */
+
+/* Substring tables.  DIRECT: one offset per substring value, 2^s + 1 uint32
+ * entries per table (the direct-address tables of Section 6, stored densely);
+ * SORTED: the substring values kept sorted beside the ids, found through a
+ * prefix directory and a binary search.  AUTO: DIRECT when it fits the
+ * memory budget, else SORTED. */
+typedef enum mih_table_mode {
+    MIH_TABLE_AUTO = 0,
+    MIH_TABLE_DIRECT = 1,
+    MIH_TABLE_SORTED = 2
+} mih_table_mode;
+
+/* Where candidate codes are read during verification.  INLINE: each table
+ * keeps a copy of the codes in its bucket order, so a bucket's codes are
+ * contiguous (m * n * bits/8 extra bytes); INDIRECT: codes are gathered from
+ * the caller's array through the ids.  AUTO: INLINE when it fits. */
+typedef enum mih_codes_mode {
+    MIH_CODES_AUTO = 0,
+    MIH_CODES_INLINE = 1,
+    MIH_CODES_INDIRECT = 2
+} mih_codes_mode;
+
+typedef struct mih_build_opts {
+    mih_table_mode table_mode;
+    mih_codes_mode codes_mode;
+    uint64_t mem_budget_bytes;   /* 0: the device memory free at build time */
+} mih_build_opts;
+
+typedef struct mih_index mih_index;   /* opaque, owned by the library */
+
+typedef struct mih_index_info {
+    uint64_t n;
+    uint32_t bits, m;
+    uint32_t table_mode;          /* MIH_TABLE_DIRECT or MIH_TABLE_SORTED  */
+    uint32_t codes_mode;          /* MIH_CODES_INLINE or MIH_CODES_INDIRECT */
+    uint32_t sub_len[MIH_M_MAX];  /* substring lengths s_j                  */
+    uint32_t sub_start[MIH_M_MAX];/* first bit of substring j               */
+    uint32_t dir_bits[MIH_M_MAX]; /* SORTED: directory bits per table       */
+    uint64_t device_bytes;        /* device memory held by the index        */
+    double build_ms;              /* wall time of mih_build                 */
+} mih_index_info;
+
+/* Device views of one table, for inspection and tests.  Pointers are owned
+ * by the index and valid until mih_free. */
+typedef struct mih_table_view {
+    const uint32_t *offsets;     /* DIRECT: [2^len + 1], else NULL          */
+    const uint32_t *keys;        /* SORTED: [n] substring values, else NULL */
+    const uint32_t *dir;         /* SORTED: [2^dir_bits + 1], else NULL     */
+    const uint32_t *ids;         /* [n] ids in bucket order                 */
+    const uint64_t *codes;       /* INLINE: [n][bits/64], else NULL         */
+    uint32_t len, start, dir_bits;
+} mih_table_view;
+
+/* Per-call counters of the multi-index search (sums over the queries). */
+typedef struct mih_query_stats {
+    uint64_t probes;       /* buckets examined (Algorithm 3 lookups)          */
+    uint64_t candidates;   /* bucket entries verified with the full distance   */
+    uint64_t appended;     /* candidates kept as possible neighbours           */
+    uint64_t steps;        /* search steps summed over queries                 */
+    uint32_t rounds;       /* device rounds (one step per active query each)   */
+    uint32_t reruns;       /* queries re-run with an exact buffer capacity     */
+    double elapsed_ms;     /* wall time of the call                            */
+    double search_kernel_ms;   /* HIP-event time of the search kernel launches */
+    uint32_t search_launches;  /* number of those launches                     */
+    uint32_t pad;
+} mih_query_stats;
+
+/* Per-call counters of the linear scan. */
+typedef struct mih_scan_stats {
+    uint64_t pairs;            /* (code, query) distances computed            */
+    uint64_t appended;         /* candidates kept as possible neighbours      */
+    uint32_t reruns;           /* queries re-run with an exact capacity       */
+    uint32_t pad;
+    double elapsed_ms;         /* wall time of the call                        */
+    double scan_kernel_ms;     /* HIP-event time of the scan kernel launches  */
+    double sample_kernel_ms;   /* HIP-event time of the initial-bound kernel  */
+} mih_scan_stats;
+
+/*
+ * Build the m substring tables of Algorithm 1 on the device.
+ *   device codes : [n][bits/64], borrowed; it must stay valid and unchanged
+ *                  until mih_free (candidates are verified against it).
+ *   n            : number of codes, 0 <= n <= 2^32 - 2.
+ *   bits         : 64, 128, 192 or 256.
+ *   m            : number of substrings, 1 <= m <= MIH_M_MAX, with
+ *                  ceil(bits / m) <= MIH_SUBSTRING_MAX.  Substring lengths are
+ *                  floor(bits/m) or ceil(bits/m), the longer ones first, each
+ *                  a run of contiguous bits (Section 2.1 and its footnote).
+ *   opts         : NULL for defaults (AUTO modes, budget = free memory).
+ *   out          : receives the index (owned by the library; release with
+ *                  mih_free).  Untouched on error.
+ */
+mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t m,
+                     const mih_build_opts *opts, void *stream, mih_index **out);
+
+/*
+ * Exact kNN of nq queries by multi-index hashing (Algorithm 3: per query, look
+ * up the buckets that differ from the query's substring in exactly r' bits,
+ * one table per step, growing r' until k codes within the searched radius are
+ * found; Propositions 1 and 2 make the result exact).
+ *   device queries     : [nq][bits/64].
+ *   k                  : neighbours per query when k_per_query is NULL.
+ *   device k_per_query : [nq] per-query k, or NULL.  Each k <= MIH_K_MAX.
+ *   device out_ids, out_dists : [sum of k_i] each, layout as above.
+ */
+mih_status mih_knn(const mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
+                   const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
+                   void *stream);
+
+/* As mih_knn, also filling *stats (may be NULL). */
+mih_status mih_knn_ex(const mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
+                      const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
+                      void *stream, mih_query_stats *stats);
+
+/*
+ * Exact kNN by linear scan (the baseline of Section 5: the distance of every
+ * code to every query, one xor and one popcount per 64 bits, Section 6).
+ * Arguments as in mih_build and mih_knn; no index is needed.
+ */
+mih_status linscan_knn(const uint64_t *codes, uint64_t n, uint32_t bits,
+                       const uint64_t *queries, uint32_t nq, uint32_t k,
+                       const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
+                       void *stream);
+
+/* As linscan_knn, also filling *stats (may be NULL). */
+mih_status linscan_knn_ex(const uint64_t *codes, uint64_t n, uint32_t bits,
+                          const uint64_t *queries, uint32_t nq, uint32_t k,
+                          const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
+                          void *stream, mih_scan_stats *stats);
+
+/* Release an index and its device memory.  NULL is ignored. */
+void mih_free(mih_index *idx);
+
+/* Static, human-readable name of a status. */
+const char *mih_status_str(mih_status s);
+
+/* Fill *info (host memory) with the index's shape and modes. */
+mih_status mih_index_get_info(const mih_index *idx, mih_index_info *info);
+
+/* Fill *view (host memory) with device pointers to table j (0 <= j < m). */
+mih_status mih_index_table(const mih_index *idx, uint32_t j, mih_table_view *view);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIH_H */

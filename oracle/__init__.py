@@ -80,6 +80,8 @@ def _lib():
         L.mihcpu_partition.restype = None
         L.mihcpu_substring.argtypes = [vp, u32, u32]
         L.mihcpu_substring.restype = u64
+        L.mihcpu_table.argtypes = [vp, u32, vp, vp]
+        L.mihcpu_table.restype = None
         _L = L
     return _L
 
@@ -186,6 +188,13 @@ class MihCpu:
             self.close()
         except Exception:
             pass
+
+    def table(self, j: int):
+        """Table j of Algorithm 1 as (values, ids) sorted by value, then id."""
+        values = np.empty(self.n, dtype=np.uint64)
+        ids = np.empty(self.n, dtype=np.uint32)
+        _lib().mihcpu_table(self._ix, j, values.ctypes.data, ids.ctypes.data)
+        return values, ids
 
     def knn(self, query, k: int):
         q = np.ascontiguousarray(query, dtype=np.uint64).reshape(-1)

@@ -288,3 +288,13 @@ uint64_t mihcpu_substring(const uint64_t *code, uint32_t start, uint32_t len)
 {
     return substring(code, start, len);
 }
+
+/* Copy table j (Algorithm 1's table as (value, id) pairs sorted by value then
+ * id) into values[n] and ids[n]. */
+void mihcpu_table(const mihcpu_index *ix, uint32_t j, uint64_t *values, uint32_t *ids)
+{
+    for (uint64_t i = 0; i < ix->n; ++i) {
+        values[i] = ix->table[j][i].value;
+        ids[i] = ix->table[j][i].id;
+    }
+}

@@ -1,0 +1,282 @@
+"""Exact Hamming kNN by multi-index hashing on AMD MI355X (gfx950).
+
+A thin ctypes binding over ``libmih.so`` (C ABI declared in
+``include/mih.h``).  PyTorch supplies device memory and the current HIP
+stream; every step of the search runs in the library's HIP kernels.  There is
+no CPU fallback: if the library is missing, loading fails with an error.
+
+    import paper_1307_2982_amd as mih
+    idx = mih.build(codes, m=2)              # codes: int64/uint64 [n, bits/64] on cuda
+    ids, dists = idx.knn(queries, k=100)     # int32 tensors, row-major [nq, k]
+    ids, dists = mih.linscan_knn(codes, queries, 100)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmih.so")
+
+SENTINEL = 0xFFFFFFFF
+K_MAX = 4096
+TABLE_MODES = {"auto": 0, "direct": 1, "sorted": 2}
+CODES_MODES = {"auto": 0, "inline": 1, "indirect": 2}
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error",
+          4: "unsupported", 5: "no capacity"}
+
+
+class MihError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("table_mode", ctypes.c_int), ("codes_mode", ctypes.c_int),
+                ("mem_budget_bytes", ctypes.c_uint64)]
+
+
+class IndexInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("bits", ctypes.c_uint32), ("m", ctypes.c_uint32),
+                ("table_mode", ctypes.c_uint32), ("codes_mode", ctypes.c_uint32),
+                ("sub_len", ctypes.c_uint32 * 64), ("sub_start", ctypes.c_uint32 * 64),
+                ("dir_bits", ctypes.c_uint32 * 64), ("device_bytes", ctypes.c_uint64),
+                ("build_ms", ctypes.c_double)]
+
+
+class TableView(ctypes.Structure):
+    _fields_ = [("offsets", ctypes.c_void_p), ("keys", ctypes.c_void_p), ("dir", ctypes.c_void_p),
+                ("ids", ctypes.c_void_p), ("codes", ctypes.c_void_p), ("len", ctypes.c_uint32),
+                ("start", ctypes.c_uint32), ("dir_bits", ctypes.c_uint32)]
+
+
+class QueryStats(ctypes.Structure):
+    _fields_ = [("probes", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
+                ("appended", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+                ("rounds", ctypes.c_uint32), ("reruns", ctypes.c_uint32),
+                ("elapsed_ms", ctypes.c_double), ("search_kernel_ms", ctypes.c_double),
+                ("search_launches", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+class ScanStats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_uint64), ("appended", ctypes.c_uint64),
+                ("reruns", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("elapsed_ms", ctypes.c_double), ("scan_kernel_ms", ctypes.c_double),
+                ("sample_kernel_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+EXPORTED = ["mih_build", "mih_knn", "mih_knn_ex", "linscan_knn", "linscan_knn_ex", "mih_free",
+            "mih_status_str", "mih_index_get_info", "mih_index_table"]
+
+_lib = None
+
+
+def lib_path() -> str:
+    return LIB_PATH
+
+
+def load():
+    """Load libmih.so (built by ``paper_1307_2982_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1307_2982_amd.buildlib` "
+                          "(the search has no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    L.mih_build.argtypes = [vp, u64, u32, u32, ctypes.POINTER(BuildOpts), vp, ctypes.POINTER(vp)]
+    L.mih_build.restype = i32
+    L.mih_knn.argtypes = [vp, vp, u32, u32, vp, vp, vp, vp]
+    L.mih_knn.restype = i32
+    L.mih_knn_ex.argtypes = [vp, vp, u32, u32, vp, vp, vp, vp, ctypes.POINTER(QueryStats)]
+    L.mih_knn_ex.restype = i32
+    L.linscan_knn.argtypes = [vp, u64, u32, vp, u32, u32, vp, vp, vp, vp]
+    L.linscan_knn.restype = i32
+    L.linscan_knn_ex.argtypes = [vp, u64, u32, vp, u32, u32, vp, vp, vp, vp, ctypes.POINTER(ScanStats)]
+    L.linscan_knn_ex.restype = i32
+    L.mih_free.argtypes = [vp]
+    L.mih_free.restype = None
+    L.mih_status_str.argtypes = [i32]
+    L.mih_status_str.restype = ctypes.c_char_p
+    L.mih_index_get_info.argtypes = [vp, ctypes.POINTER(IndexInfo)]
+    L.mih_index_get_info.restype = i32
+    L.mih_index_table.argtypes = [vp, u32, ctypes.POINTER(TableView)]
+    L.mih_index_table.restype = i32
+    _lib = L
+    return L
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _codes_arg(t: torch.Tensor, what: str):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise TypeError(f"{what} must be int64 or uint64 words, got {t.dtype}")
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous [rows, bits/64] tensor")
+    return t
+
+
+def _k_arg(k, nq: int, device):
+    """Returns (scalar k, device k tensor or None, per-query k list)."""
+    if isinstance(k, int):
+        return k, None, None
+    kt = torch.as_tensor(k, dtype=torch.int32)
+    if kt.numel() != nq:
+        raise ValueError("k_per_query must have one entry per query")
+    kl = kt.cpu().tolist()
+    return 0, kt.to(device).contiguous(), kl
+
+
+def _outputs(nq: int, k: int, kl, device):
+    total = sum(kl) if kl is not None else nq * k
+    ids = torch.empty(max(total, 1), dtype=torch.int32, device=device)
+    dists = torch.empty(max(total, 1), dtype=torch.int32, device=device)
+    return ids, dists, total
+
+
+def _shape(ids, dists, total, nq, k, kl):
+    ids, dists = ids[:total], dists[:total]
+    if kl is None:
+        return ids.view(nq, k), dists.view(nq, k)
+    return ids, dists
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise MihError(status, what)
+
+
+class Index:
+    """A multi-index hashing index over device codes (borrowed, kept alive here)."""
+
+    def __init__(self, handle, codes: torch.Tensor):
+        self._h = handle
+        self.codes = codes
+
+    def close(self):
+        if self._h:
+            load().mih_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = IndexInfo()
+        _check(load().mih_index_get_info(self._h, ctypes.byref(inf)), "mih_index_get_info")
+        m = inf.m
+        return {"n": inf.n, "bits": inf.bits, "m": m,
+                "table_mode": {1: "direct", 2: "sorted"}.get(inf.table_mode, inf.table_mode),
+                "codes_mode": {1: "inline", 2: "indirect"}.get(inf.codes_mode, inf.codes_mode),
+                "sub_len": list(inf.sub_len[:m]), "sub_start": list(inf.sub_start[:m]),
+                "dir_bits": list(inf.dir_bits[:m]), "device_bytes": inf.device_bytes,
+                "build_ms": inf.build_ms}
+
+    def table(self, j: int) -> dict:
+        """Copies of table j's device arrays (as CPU tensors), for inspection."""
+        v = TableView()
+        _check(load().mih_index_table(self._h, j, ctypes.byref(v)), "mih_index_table")
+        n = self.codes.shape[0]
+        W = self.codes.shape[1]
+        out = {"len": v.len, "start": v.start, "dir_bits": v.dir_bits}
+        out["ids"] = _copy_device(v.ids, n, torch.int32)
+        if v.offsets:
+            out["offsets"] = _copy_device(v.offsets, (1 << v.len) + 1, torch.int32)
+        if v.keys:
+            out["keys"] = _copy_device(v.keys, n, torch.int32)
+        if v.dir:
+            out["dir"] = _copy_device(v.dir, (1 << v.dir_bits) + 1, torch.int32)
+        if v.codes:
+            out["codes"] = _copy_device(v.codes, n * W, torch.int64).view(n, W)
+        return out
+
+    def knn(self, queries: torch.Tensor, k, stats: bool = False):
+        """Exact kNN; k is an int or a per-query sequence (then rows are flat)."""
+        queries = _codes_arg(queries, "queries")
+        if queries.shape[1] != self.codes.shape[1]:
+            raise ValueError("queries and codes differ in length")
+        nq = queries.shape[0]
+        kk, kt, kl = _k_arg(k, nq, queries.device)
+        ids, dists, total = _outputs(nq, kk, kl, queries.device)
+        st = QueryStats()
+        rc = load().mih_knn_ex(self._h, queries.data_ptr(), nq, kk,
+                               kt.data_ptr() if kt is not None else None,
+                               ids.data_ptr(), dists.data_ptr(), _stream(), ctypes.byref(st))
+        _check(rc, "mih_knn")
+        ids, dists = _shape(ids, dists, total, nq, kk, kl)
+        return (ids, dists, st.as_dict()) if stats else (ids, dists)
+
+
+def build(codes: torch.Tensor, m: int, table_mode: str = "auto", codes_mode: str = "auto",
+          mem_budget_bytes: int = 0) -> Index:
+    """Build the m substring tables (Algorithm 1) on the device."""
+    codes = _codes_arg(codes, "codes")
+    n, W = codes.shape
+    opts = BuildOpts(TABLE_MODES[table_mode], CODES_MODES[codes_mode], mem_budget_bytes)
+    h = ctypes.c_void_p()
+    rc = load().mih_build(codes.data_ptr() if n else None, n, 64 * W, m, ctypes.byref(opts),
+                          _stream(), ctypes.byref(h))
+    _check(rc, "mih_build")
+    return Index(h, codes)
+
+
+def linscan_knn(codes: torch.Tensor, queries: torch.Tensor, k, stats: bool = False):
+    """Exact kNN by the GPU linear scan."""
+    codes = _codes_arg(codes, "codes")
+    queries = _codes_arg(queries, "queries")
+    if queries.shape[1] != codes.shape[1]:
+        raise ValueError("queries and codes differ in length")
+    n, W = codes.shape
+    nq = queries.shape[0]
+    kk, kt, kl = _k_arg(k, nq, queries.device)
+    ids, dists, total = _outputs(nq, kk, kl, queries.device)
+    st = ScanStats()
+    rc = load().linscan_knn_ex(codes.data_ptr() if n else None, n, 64 * W, queries.data_ptr(), nq,
+                               kk, kt.data_ptr() if kt is not None else None, ids.data_ptr(),
+                               dists.data_ptr(), _stream(), ctypes.byref(st))
+    _check(rc, "linscan_knn")
+    ids, dists = _shape(ids, dists, total, nq, kk, kl)
+    return (ids, dists, st.as_dict()) if stats else (ids, dists)
+
+
+# ------------------------------------------------------------------ plumbing
+
+_hip = None
+
+
+def _hip_runtime():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so.7")   # the runtime torch has loaded
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    return _hip
+
+
+def _copy_device(ptr, count: int, dtype) -> torch.Tensor:
+    """Copy `count` elements at a device pointer owned by the library to CPU."""
+    out = torch.empty(max(count, 1), dtype=dtype, device="cuda")
+    nbytes = count * out.element_size()
+    if nbytes:
+        torch.cuda.synchronize()
+        rc = _hip_runtime().hipMemcpy(out.data_ptr(), ptr, nbytes, 3)   # device to device
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy failed ({rc})")
+    return out[:count].cpu()

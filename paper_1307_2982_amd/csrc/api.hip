@@ -1,0 +1,818 @@
+// C-ABI entry points (include/mih.h): argument checks, device memory
+// planning, the host side of the round loop, and the exact re-run of queries
+// whose candidate buffer overflowed.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "mih_common.h"
+#include "mih_query.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+double ms_since(clk::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+// Status of a failed HIP call; with MIH_DEBUG set in the environment the
+// call site and the runtime's message go to stderr.
+mih_status from_hip_at(hipError_t e, int line)
+{
+    if (e == hipSuccess) return MIH_OK;
+    static const bool debug = std::getenv("MIH_DEBUG") != nullptr;
+    if (debug) std::fprintf(stderr, "libmih: api.hip:%d: %s\n", line, hipGetErrorString(e));
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return MIH_ERR_NOMEM;
+    return MIH_ERR_DEVICE;
+}
+#define from_hip(e) from_hip_at((e), __LINE__)
+
+#define MIH_TRY(expr)                              \
+    do {                                           \
+        hipError_t e_ = (expr);                    \
+        if (e_ != hipSuccess) {                    \
+            (void)hipGetLastError();               \
+            return from_hip(e_);                   \
+        }                                          \
+    } while (0)
+
+#define MIH_TRY_STATUS(expr)                       \
+    do {                                           \
+        mih_status st_ = (expr);                   \
+        if (st_ != MIH_OK) return st_;             \
+    } while (0)
+
+bool bits_ok(uint32_t bits) { return bits == 64 || bits == 128 || bits == 192 || bits == 256; }
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+uint32_t ceil_log2(uint64_t x)
+{
+    uint32_t b = 0;
+    while ((1ull << b) < x) ++b;
+    return b;
+}
+
+uint32_t num_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 256;
+    return (uint32_t)cus;
+}
+
+// A device region carved into aligned pieces.  With base == nullptr it only
+// measures the size that the same sequence of take() calls needs.
+struct Carver {
+    char *base = nullptr;
+    uint64_t used = 0;
+    template <class T>
+    T *take(uint64_t count)
+    {
+        uint64_t bytes = align_up((count ? count : 1) * sizeof(T), 256);
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += bytes;
+        return p;
+    }
+};
+
+// Grow-only device scratch.
+struct Scratch {
+    void *ptr = nullptr;
+    uint64_t size = 0;
+    hipError_t ensure(uint64_t bytes)
+    {
+        if (bytes <= size) return hipSuccess;
+        if (ptr) { (void)hipFree(ptr); ptr = nullptr; size = 0; }
+        hipError_t e = hipMalloc(&ptr, bytes);
+        if (e == hipSuccess) size = bytes;
+        else (void)hipGetLastError();
+        return e;
+    }
+    void release()
+    {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        size = 0;
+    }
+};
+
+// A pair of HIP events around launches on one stream (disabled unless the
+// caller asked for statistics).
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on = false;
+    explicit EventPair(bool enable)
+    {
+        if (!enable) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        on = true;
+    }
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    void begin(hipStream_t s) { if (on) (void)hipEventRecord(a, s); }
+    void end(hipStream_t s) { if (on) (void)hipEventRecord(b, s); }
+    // milliseconds between the two records (waits for the second)
+    double ms()
+    {
+        float t = 0;
+        if (!on || hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&t, a, b) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0.0;
+        }
+        return t;
+    }
+};
+
+// Host description of a batch of queries.
+struct BatchSpec {
+    const uint64_t *queries = nullptr;   // device [nq][W]
+    uint32_t nq = 0;
+    std::vector<uint32_t> k;             // per query
+    std::vector<uint64_t> row_off;       // output offset per query
+    std::vector<uint32_t> cap;           // buffer capacity per query
+    const uint32_t *tau0 = nullptr;      // device, or null
+};
+
+struct BatchBufs {
+    QueryBatch qb;
+    uint64_t *row_off;
+    uint32_t *ovf_list, *ovf_count;
+    uint32_t *t, *active0, *active1, *next_t;
+    mih::Group *groups;
+    mih::Control *ctrl;
+    unsigned long long *work, *stats;
+};
+
+void carve_batch(Carver &c, const BatchSpec &b, uint32_t bits, uint32_t W, uint64_t buf_words,
+                 uint32_t ngroups, BatchBufs &B)
+{
+    const uint32_t nq = b.nq;
+    B.qb.k = c.take<uint32_t>(nq);
+    B.qb.tau = c.take<uint32_t>(nq);
+    B.qb.count = c.take<uint32_t>(nq);
+    B.qb.cap = c.take<uint32_t>(nq);
+    B.qb.buf_off = c.take<uint64_t>(nq);
+    B.qb.hist = c.take<uint32_t>((uint64_t)nq * (bits + 1));
+    B.qb.buf = c.take<uint64_t>(buf_words);
+    B.row_off = c.take<uint64_t>(nq);
+    B.ovf_list = c.take<uint32_t>(nq);
+    B.ovf_count = c.take<uint32_t>(1);
+    B.t = c.take<uint32_t>(nq);
+    B.active0 = c.take<uint32_t>(nq);
+    B.active1 = c.take<uint32_t>(nq);
+    B.next_t = c.take<uint32_t>(nq);
+    B.groups = c.take<mih::Group>(ngroups);
+    B.ctrl = c.take<mih::Control>(1);
+    B.work = c.take<unsigned long long>(1);
+    B.stats = c.take<unsigned long long>(4);
+    B.qb.queries = b.queries;
+    B.qb.nq = nq;
+    B.qb.bits = bits;
+    (void)W;
+}
+
+uint64_t buffer_words(const BatchSpec &b, std::vector<uint64_t> &buf_off)
+{
+    buf_off.resize(b.nq);
+    uint64_t acc = 0;
+    for (uint32_t i = 0; i < b.nq; ++i) { buf_off[i] = acc; acc += b.cap[i]; }
+    return acc;
+}
+
+hipError_t upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (!bytes) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);   // the host vectors are freed soon after
+}
+
+hipError_t download(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (!bytes) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+// Per-query k as host vector; validates k <= MIH_K_MAX.
+mih_status read_k(uint32_t nq, uint32_t k, const uint32_t *k_per_query, hipStream_t s,
+                  std::vector<uint32_t> &out)
+{
+    out.assign(nq, k);
+    if (k_per_query && nq) MIH_TRY(download(out.data(), k_per_query, sizeof(uint32_t) * nq, s));
+    for (uint32_t v : out)
+        if (v > MIH_K_MAX) return MIH_ERR_UNSUPPORTED;
+    return MIH_OK;
+}
+
+void row_offsets(const std::vector<uint32_t> &k, std::vector<uint64_t> &off)
+{
+    off.resize(k.size());
+    uint64_t acc = 0;
+    for (size_t i = 0; i < k.size(); ++i) { off[i] = acc; acc += k[i]; }
+}
+
+uint32_t mih_cap(uint32_t k) { return k == 0 ? 0u : std::max<uint32_t>(2048u, 8u * k); }
+uint32_t scan_cap(uint32_t k) { return k == 0 ? 0u : std::max<uint32_t>(4096u, 16u * k); }
+
+}  // namespace
+
+// ============================================================== the index
+
+struct mih_index {
+    int device = 0;
+    const uint64_t *codes = nullptr;
+    uint64_t n = 0;
+    uint32_t bits = 0, W = 0, m = 0;
+    uint32_t table_mode = 0, codes_mode = 0;
+    uint32_t len[MIH_M_MAX] = {}, start[MIH_M_MAX] = {}, dir_bits[MIH_M_MAX] = {};
+    uint32_t t_all = 0;
+    TableDev tables_host[MIH_M_MAX] = {};
+    TableDev *tables_dev = nullptr;
+    std::vector<void *> allocs;
+    uint64_t device_bytes = 0;
+    double build_ms = 0;
+    uint32_t chunk = 1024;
+    std::mutex mu;
+    Scratch scratch, rerun_scratch;
+    mih::Control *ctrl_host = nullptr;   // pinned
+
+    hipError_t alloc(void **p, uint64_t bytes)
+    {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 4);
+        if (e != hipSuccess) { (void)hipGetLastError(); *p = nullptr; return e; }
+        allocs.push_back(*p);
+        device_bytes += bytes;
+        return hipSuccess;
+    }
+    ~mih_index()
+    {
+        for (void *p : allocs) (void)hipFree(p);
+        scratch.release();
+        rerun_scratch.release();
+        if (ctrl_host) (void)hipHostFree(ctrl_host);
+    }
+};
+
+namespace {
+
+// ---------------------------------------------------------------- linscan
+
+mih_status linscan_batch(const uint64_t *codes, uint64_t n, uint32_t bits, BatchSpec &b,
+                         uint32_t *out_ids, uint32_t *out_dists, hipStream_t s, int depth,
+                         mih_scan_stats *stats);
+
+mih_status rerun_linscan(const uint64_t *codes, uint64_t n, uint32_t bits, const BatchSpec &b,
+                         BatchBufs &B, uint32_t *out_ids, uint32_t *out_dists, hipStream_t s,
+                         int depth, mih_scan_stats *stats)
+{
+    uint32_t novf = 0;
+    MIH_TRY(download(&novf, B.ovf_count, sizeof(uint32_t), s));
+    if (novf == 0) return MIH_OK;
+    if (depth > 2) return MIH_ERR_DEVICE;   // an exact re-run cannot overflow
+    if (stats) stats->reruns += novf;
+    const uint32_t W = bits / 64;
+    std::vector<uint32_t> list(novf);
+    MIH_TRY(download(list.data(), B.ovf_list, sizeof(uint32_t) * novf, s));
+    Carver c0;
+    c0.take<uint32_t>(novf); c0.take<uint32_t>(novf); c0.take<uint32_t>(novf);
+    c0.take<uint64_t>((uint64_t)novf * W);
+    Scratch tmp;
+    MIH_TRY(tmp.ensure(c0.used));
+    Carver c;
+    c.base = (char *)tmp.ptr;
+    uint32_t *dlist = c.take<uint32_t>(novf);
+    uint32_t *dtau = c.take<uint32_t>(novf);
+    uint32_t *dcap = c.take<uint32_t>(novf);
+    uint64_t *dq = c.take<uint64_t>((uint64_t)novf * W);
+    mih_status st = MIH_OK;
+    do {
+        if (upload(dlist, list.data(), sizeof(uint32_t) * novf, s) != hipSuccess) { st = MIH_ERR_DEVICE; break; }
+        if (mih::exact_bounds(B.qb, dlist, novf, dtau, dcap, s) != hipSuccess ||
+            mih::gather_rows(b.queries, dlist, novf, W, dq, s) != hipSuccess) { st = MIH_ERR_DEVICE; break; }
+        BatchSpec rb;
+        rb.queries = dq;
+        rb.nq = novf;
+        rb.tau0 = dtau;
+        rb.cap.resize(novf);
+        if (download(rb.cap.data(), dcap, sizeof(uint32_t) * novf, s) != hipSuccess) { st = MIH_ERR_DEVICE; break; }
+        rb.k.resize(novf);
+        rb.row_off.resize(novf);
+        for (uint32_t i = 0; i < novf; ++i) {
+            rb.k[i] = b.k[list[i]];
+            rb.row_off[i] = b.row_off[list[i]];
+            if (rb.cap[i] == 0 && rb.k[i]) rb.cap[i] = 1;
+        }
+        st = linscan_batch(codes, n, bits, rb, out_ids, out_dists, s, depth + 1, stats);
+    } while (0);
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    return st;
+}
+
+mih_status linscan_batch(const uint64_t *codes, uint64_t n, uint32_t bits, BatchSpec &b,
+                         uint32_t *out_ids, uint32_t *out_dists, hipStream_t s, int depth,
+                         mih_scan_stats *stats)
+{
+    if (b.nq == 0) return MIH_OK;
+    const uint32_t W = bits / 64;
+    std::vector<uint64_t> buf_off;
+    const uint64_t words = buffer_words(b, buf_off);
+    BatchBufs B;
+    Carver c0;
+    carve_batch(c0, b, bits, W, words, 1, B);
+    Scratch mem;
+    MIH_TRY(mem.ensure(c0.used));
+    Carver c;
+    c.base = (char *)mem.ptr;
+    carve_batch(c, b, bits, W, words, 1, B);
+    mih_status st = MIH_OK;
+    do {
+        hipError_t e = upload((void *)B.qb.k, b.k.data(), sizeof(uint32_t) * b.nq, s);
+        if (e == hipSuccess) e = upload((void *)B.qb.cap, b.cap.data(), sizeof(uint32_t) * b.nq, s);
+        if (e == hipSuccess) e = upload((void *)B.qb.buf_off, buf_off.data(), sizeof(uint64_t) * b.nq, s);
+        if (e == hipSuccess) e = upload(B.row_off, b.row_off.data(), sizeof(uint64_t) * b.nq, s);
+        mih::LinscanArgs L;
+        L.codes = codes;
+        L.n = n;
+        L.qb = B.qb;
+        L.W = W;
+        uint32_t kmax = 0;
+        for (uint32_t v : b.k) kmax = std::max(kmax, v);
+        uint64_t sample = std::min<uint64_t>(n, std::max<uint64_t>(65536, 256ull * kmax));
+        if (sample > (1ull << 20)) sample = 1ull << 20;
+        EventPair ev_sample(stats != nullptr), ev_scan(stats != nullptr);
+        ev_sample.begin(s);
+        if (e == hipSuccess) e = mih::linscan_init(L, sample, b.tau0, s);
+        ev_sample.end(s);
+        ev_scan.begin(s);
+        if (e == hipSuccess) e = mih::linscan_run(L, num_cus(), s);
+        ev_scan.end(s);
+        mih::FinalArgs F;
+        F.qb = B.qb;
+        F.row_off = B.row_off;
+        F.out_ids = out_ids;
+        F.out_dists = out_dists;
+        F.overflow_list = B.ovf_list;
+        F.overflow_count = B.ovf_count;
+        if (e == hipSuccess) e = mih::find_overflow(F, s);
+        if (e == hipSuccess) e = mih::finalize_topk(F, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { (void)hipGetLastError(); st = from_hip(e); break; }
+        if (stats) {
+            stats->sample_kernel_ms += ev_sample.ms();
+            stats->scan_kernel_ms += ev_scan.ms();
+            stats->pairs += n * (uint64_t)b.nq;
+            std::vector<uint32_t> cnt(b.nq);
+            if (download(cnt.data(), B.qb.count, sizeof(uint32_t) * b.nq, s) == hipSuccess)
+                for (uint32_t i = 0; i < b.nq; ++i) stats->appended += cnt[i];
+        }
+        st = rerun_linscan(codes, n, bits, b, B, out_ids, out_dists, s, depth, stats);
+    } while (0);
+    (void)hipStreamSynchronize(s);
+    mem.release();
+    return st;
+}
+
+// ---------------------------------------------------------------- MIH
+
+mih_status mih_batch(mih_index *ix, BatchSpec &b, uint32_t *out_ids, uint32_t *out_dists,
+                     hipStream_t s, Scratch &mem, int depth, mih_query_stats *stats);
+
+mih_status rerun_mih(mih_index *ix, const BatchSpec &b, BatchBufs &B, uint32_t *out_ids,
+                     uint32_t *out_dists, hipStream_t s, int depth, mih_query_stats *stats)
+{
+    uint32_t novf = 0;
+    MIH_TRY(download(&novf, B.ovf_count, sizeof(uint32_t), s));
+    if (novf == 0) return MIH_OK;
+    if (depth > 2) return MIH_ERR_DEVICE;
+    if (stats) stats->reruns += novf;
+    const uint32_t W = ix->W;
+    std::vector<uint32_t> list(novf);
+    MIH_TRY(download(list.data(), B.ovf_list, sizeof(uint32_t) * novf, s));
+    Carver c0;
+    c0.take<uint32_t>(novf); c0.take<uint32_t>(novf); c0.take<uint32_t>(novf);
+    c0.take<uint64_t>((uint64_t)novf * W);
+    Scratch tmp;
+    MIH_TRY(tmp.ensure(c0.used));
+    Carver c;
+    c.base = (char *)tmp.ptr;
+    uint32_t *dlist = c.take<uint32_t>(novf);
+    uint32_t *dtau = c.take<uint32_t>(novf);
+    uint32_t *dcap = c.take<uint32_t>(novf);
+    uint64_t *dq = c.take<uint64_t>((uint64_t)novf * W);
+    mih_status st = MIH_OK;
+    do {
+        if (upload(dlist, list.data(), sizeof(uint32_t) * novf, s) != hipSuccess) { st = MIH_ERR_DEVICE; break; }
+        if (mih::exact_bounds(B.qb, dlist, novf, dtau, dcap, s) != hipSuccess ||
+            mih::gather_rows(b.queries, dlist, novf, W, dq, s) != hipSuccess) { st = MIH_ERR_DEVICE; break; }
+        BatchSpec rb;
+        rb.queries = dq;
+        rb.nq = novf;
+        rb.tau0 = dtau;
+        rb.cap.resize(novf);
+        if (download(rb.cap.data(), dcap, sizeof(uint32_t) * novf, s) != hipSuccess) { st = MIH_ERR_DEVICE; break; }
+        rb.k.resize(novf);
+        rb.row_off.resize(novf);
+        for (uint32_t i = 0; i < novf; ++i) {
+            rb.k[i] = b.k[list[i]];
+            rb.row_off[i] = b.row_off[list[i]];
+            if (rb.cap[i] == 0 && rb.k[i]) rb.cap[i] = 1;
+        }
+        st = mih_batch(ix, rb, out_ids, out_dists, s, ix->rerun_scratch, depth + 1, stats);
+    } while (0);
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    return st;
+}
+
+mih_status mih_batch(mih_index *ix, BatchSpec &b, uint32_t *out_ids, uint32_t *out_dists,
+                     hipStream_t s, Scratch &mem, int depth, mih_query_stats *stats)
+{
+    if (b.nq == 0) return MIH_OK;
+    const uint32_t W = ix->W, bits = ix->bits;
+    std::vector<uint64_t> buf_off;
+    const uint64_t words = buffer_words(b, buf_off);
+    BatchBufs B;
+    Carver c0;
+    carve_batch(c0, b, bits, W, words, ix->t_all + 1, B);
+    MIH_TRY(mem.ensure(c0.used));
+    Carver c;
+    c.base = (char *)mem.ptr;
+    carve_batch(c, b, bits, W, words, ix->t_all + 1, B);
+
+    std::vector<uint32_t> active;
+    active.reserve(b.nq);
+    for (uint32_t i = 0; i < b.nq; ++i)
+        if (b.k[i]) active.push_back(i);
+    mih::Group g0 = {0, (uint32_t)active.size(), 1, 0, 0};
+    mih::Control c_init = {(uint32_t)active.size(), 1, (uint64_t)active.size()};
+
+    MIH_TRY(upload((void *)B.qb.k, b.k.data(), sizeof(uint32_t) * b.nq, s));
+    MIH_TRY(upload((void *)B.qb.cap, b.cap.data(), sizeof(uint32_t) * b.nq, s));
+    MIH_TRY(upload((void *)B.qb.buf_off, buf_off.data(), sizeof(uint64_t) * b.nq, s));
+    MIH_TRY(upload(B.row_off, b.row_off.data(), sizeof(uint64_t) * b.nq, s));
+    MIH_TRY(upload(B.active0, active.data(), sizeof(uint32_t) * active.size(), s));
+    MIH_TRY(upload(B.groups, &g0, sizeof(g0), s));
+    MIH_TRY(upload(B.ctrl, &c_init, sizeof(c_init), s));
+    MIH_TRY(mih::fill_u32(B.qb.count, b.nq, 0u, s));
+    MIH_TRY(mih::fill_u32(B.qb.hist, (uint64_t)b.nq * (bits + 1), 0u, s));
+    MIH_TRY(mih::fill_u32(B.t, b.nq, 0u, s));
+    MIH_TRY(mih::fill_u64((uint64_t *)B.work, 1, 0ull, s));
+    MIH_TRY(mih::fill_u64((uint64_t *)B.stats, 4, 0ull, s));
+    if (b.tau0)
+        MIH_TRY(hipMemcpyAsync(B.qb.tau, b.tau0, sizeof(uint32_t) * b.nq, hipMemcpyDeviceToDevice, s));
+    else
+        MIH_TRY(mih::fill_u32(B.qb.tau, b.nq, bits, s));
+
+    mih::MihArgs A;
+    A.tables = ix->tables_dev;
+    A.codes = ix->codes;
+    A.n = ix->n;
+    A.W = W;
+    A.m = ix->m;
+    A.bits = bits;
+    A.t_all = ix->t_all;
+    A.sorted = ix->table_mode == MIH_TABLE_SORTED;
+    A.inline_codes = ix->codes_mode == MIH_CODES_INLINE;
+    A.chunk = ix->chunk;
+    A.qb = B.qb;
+    A.t = B.t;
+    A.groups = B.groups;
+    A.ctrl = B.ctrl;
+    A.work = B.work;
+    A.stats = B.stats;
+    const uint32_t grid = num_cus() * (uint32_t)mih::mih_round_occupancy(W, A.sorted, A.inline_codes);
+
+    uint32_t n_active = (uint32_t)active.size();
+    uint32_t *cur = B.active0, *nxt = B.active1;
+    uint32_t rounds = 0;
+    EventPair ev_round(stats != nullptr);
+    while (n_active > 0) {
+        if (rounds > 4 * ix->t_all + 16) return MIH_ERR_DEVICE;   // cannot happen: t grows each round
+        A.active = cur;
+        ev_round.begin(s);
+        MIH_TRY(mih::mih_round(A, grid, s));
+        ev_round.end(s);
+        MIH_TRY(mih::mih_advance(A, b.nq, B.next_t, nxt, B.groups, B.ctrl, s));
+        MIH_TRY(hipMemcpyAsync(ix->ctrl_host, B.ctrl, sizeof(mih::Control), hipMemcpyDeviceToHost, s));
+        MIH_TRY(hipStreamSynchronize(s));
+        n_active = ix->ctrl_host->n_active;
+        std::swap(cur, nxt);
+        ++rounds;
+        if (stats) {
+            stats->search_kernel_ms += ev_round.ms();
+            stats->search_launches += 1;
+        }
+    }
+
+    mih::FinalArgs F;
+    F.qb = B.qb;
+    F.row_off = B.row_off;
+    F.out_ids = out_ids;
+    F.out_dists = out_dists;
+    F.overflow_list = B.ovf_list;
+    F.overflow_count = B.ovf_count;
+    MIH_TRY(mih::find_overflow(F, s));
+    MIH_TRY(mih::finalize_topk(F, s));
+    MIH_TRY(hipStreamSynchronize(s));
+    if (stats) {
+        unsigned long long st4[4] = {0, 0, 0, 0};
+        MIH_TRY(download(st4, B.stats, sizeof(st4), s));
+        std::vector<uint32_t> t(b.nq), cnt(b.nq);
+        MIH_TRY(download(t.data(), B.t, sizeof(uint32_t) * b.nq, s));
+        MIH_TRY(download(cnt.data(), B.qb.count, sizeof(uint32_t) * b.nq, s));
+        stats->probes += st4[0];
+        stats->candidates += st4[1];
+        for (uint32_t i = 0; i < b.nq; ++i)
+            if (b.k[i]) { stats->steps += (uint64_t)t[i] + 1; stats->appended += cnt[i]; }
+        stats->rounds += rounds;
+    }
+    return rerun_mih(ix, b, B, out_ids, out_dists, s, depth, stats);
+}
+
+mih_status check_query_args(uint32_t bits, const uint64_t *queries, uint32_t nq,
+                            const uint32_t *out_ids, const uint32_t *out_dists)
+{
+    if (!bits_ok(bits)) return MIH_ERR_INVALID;
+    if (nq && !queries) return MIH_ERR_INVALID;
+    if (nq && (!out_ids || !out_dists)) return MIH_ERR_INVALID;
+    if (((uintptr_t)queries & 7) != 0) return MIH_ERR_INVALID;
+    return MIH_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+const char *mih_status_str(mih_status s)
+{
+    switch (s) {
+    case MIH_OK: return "ok";
+    case MIH_ERR_INVALID: return "invalid argument";
+    case MIH_ERR_NOMEM: return "out of device memory";
+    case MIH_ERR_DEVICE: return "device error";
+    case MIH_ERR_UNSUPPORTED: return "unsupported";
+    case MIH_ERR_CAPACITY: return "no capacity";
+    }
+    return "unknown status";
+}
+
+mih_status linscan_knn(const uint64_t *codes, uint64_t n, uint32_t bits, const uint64_t *queries,
+                       uint32_t nq, uint32_t k, const uint32_t *k_per_query, uint32_t *out_ids,
+                       uint32_t *out_dists, void *stream)
+{
+    return linscan_knn_ex(codes, n, bits, queries, nq, k, k_per_query, out_ids, out_dists, stream,
+                          nullptr);
+}
+
+mih_status linscan_knn_ex(const uint64_t *codes, uint64_t n, uint32_t bits, const uint64_t *queries,
+                          uint32_t nq, uint32_t k, const uint32_t *k_per_query, uint32_t *out_ids,
+                          uint32_t *out_dists, void *stream, mih_scan_stats *stats)
+{
+    auto t0 = clk::now();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    MIH_TRY_STATUS(check_query_args(bits, queries, nq, out_ids, out_dists));
+    if (n > 0xFFFFFFFEull || (n && !codes) || ((uintptr_t)codes & 7) != 0) return MIH_ERR_INVALID;
+    if (!k_per_query && k > MIH_K_MAX) return MIH_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    BatchSpec b;
+    b.queries = queries;
+    b.nq = nq;
+    MIH_TRY_STATUS(read_k(nq, k, k_per_query, s, b.k));
+    row_offsets(b.k, b.row_off);
+    b.cap.resize(nq);
+    for (uint32_t i = 0; i < nq; ++i) b.cap[i] = scan_cap(b.k[i]);
+    if (n == 0) {
+        // nothing to scan: every row is padding
+        uint64_t total = b.row_off.empty() ? 0 : b.row_off.back() + b.k.back();
+        MIH_TRY(mih::fill_u32(out_ids, total, MIH_SENTINEL, s));
+        MIH_TRY(mih::fill_u32(out_dists, total, MIH_SENTINEL, s));
+        MIH_TRY(hipStreamSynchronize(s));
+        return MIH_OK;
+    }
+    mih_status st = linscan_batch(codes, n, bits, b, out_ids, out_dists, s, 0, stats);
+    if (stats) stats->elapsed_ms = ms_since(t0);
+    return st;
+}
+
+mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t m,
+                     const mih_build_opts *opts, void *stream, mih_index **out)
+{
+    auto t0 = clk::now();
+    if (!out) return MIH_ERR_INVALID;
+    if (!bits_ok(bits) || m < 1 || m > MIH_M_MAX || m > bits) return MIH_ERR_INVALID;
+    if ((bits + m - 1) / m > MIH_SUBSTRING_MAX) return MIH_ERR_UNSUPPORTED;
+    if (n > 0xFFFFFFFEull || (n && !codes) || ((uintptr_t)codes & 7) != 0) return MIH_ERR_INVALID;
+    mih_build_opts o = {MIH_TABLE_AUTO, MIH_CODES_AUTO, 0};
+    if (opts) o = *opts;
+    if (o.table_mode > MIH_TABLE_SORTED || o.codes_mode > MIH_CODES_INDIRECT) return MIH_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+
+    mih_index *ix = new (std::nothrow) mih_index();
+    if (!ix) return MIH_ERR_NOMEM;
+    (void)hipGetDevice(&ix->device);
+    ix->codes = codes;
+    ix->n = n;
+    ix->bits = bits;
+    ix->W = bits / 64;
+    ix->m = m;
+    const uint32_t W = ix->W;
+    {
+        uint32_t base = bits / m, extra = bits % m, st = 0;
+        ix->t_all = 0xFFFFFFFFu;
+        for (uint32_t j = 0; j < m; ++j) {
+            ix->len[j] = base + (j < extra ? 1 : 0);
+            ix->start[j] = st;
+            st += ix->len[j];
+            ix->t_all = std::min(ix->t_all, m * ix->len[j] + j);
+        }
+    }
+    const uint32_t lg = ceil_log2(n + 1);
+    uint64_t direct_bytes = 0, sorted_bytes = 0, max_entries = n + 1;
+    for (uint32_t j = 0; j < m; ++j) {
+        uint32_t p = lg > 3 ? lg - 3 : 1;
+        if (p > ix->len[j]) p = ix->len[j];
+        if (p < 1) p = 1;
+        ix->dir_bits[j] = p;
+        direct_bytes += ((1ull << ix->len[j]) + 1) * 4;
+        sorted_bytes += n * 4 + ((1ull << p) + 1) * 4;
+        max_entries = std::max<uint64_t>(max_entries, (1ull << ix->len[j]) + 1);
+    }
+    const uint64_t ids_bytes = (uint64_t)m * n * 4;
+    const uint64_t inline_bytes = (uint64_t)m * n * 8 * W;
+    const uint64_t temp_bytes = 3 * n * 4 + mih::radix_tmp_words(n) * 4 +
+                                mih::scan_tmp_words(max_entries) * 4 + (1 << 20);
+    uint64_t budget = o.mem_budget_bytes;
+    if (!budget) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); delete ix; return MIH_ERR_DEVICE; }
+        budget = fr;
+    }
+    const uint64_t reserve = std::min<uint64_t>(8ull << 30, budget / 10);
+    uint64_t need = ids_bytes + temp_bytes + reserve;
+    if (o.table_mode == MIH_TABLE_DIRECT) ix->table_mode = MIH_TABLE_DIRECT;
+    else if (o.table_mode == MIH_TABLE_SORTED) ix->table_mode = MIH_TABLE_SORTED;
+    else ix->table_mode = need + direct_bytes <= budget ? MIH_TABLE_DIRECT : MIH_TABLE_SORTED;
+    need += ix->table_mode == MIH_TABLE_DIRECT ? direct_bytes : sorted_bytes;
+    if (o.codes_mode == MIH_CODES_INLINE) ix->codes_mode = MIH_CODES_INLINE;
+    else if (o.codes_mode == MIH_CODES_INDIRECT) ix->codes_mode = MIH_CODES_INDIRECT;
+    else ix->codes_mode = need + inline_bytes <= budget ? MIH_CODES_INLINE : MIH_CODES_INDIRECT;
+    if (ix->codes_mode == MIH_CODES_INLINE) need += inline_bytes;
+    if (o.mem_budget_bytes && need - reserve > budget) { delete ix; return MIH_ERR_NOMEM; }
+
+    mih_status st = MIH_OK;
+    Scratch tk1, tk2, ti2, tmp;
+    do {
+        hipError_t e = hipHostMalloc((void **)&ix->ctrl_host, sizeof(mih::Control), 0);
+        if (e != hipSuccess) { st = from_hip(e); break; }
+        if ((e = tk1.ensure(n * 4 + 4)) != hipSuccess || (e = tk2.ensure(n * 4 + 4)) != hipSuccess ||
+            (e = ti2.ensure(n * 4 + 4)) != hipSuccess ||
+            (e = tmp.ensure(std::max(mih::radix_tmp_words(n), mih::scan_tmp_words(max_entries)) * 4)) !=
+                hipSuccess) {
+            st = from_hip(e);
+            break;
+        }
+        for (uint32_t j = 0; j < m && st == MIH_OK; ++j) {
+            TableDev &T = ix->tables_host[j];
+            T.len = ix->len[j];
+            T.start = ix->start[j];
+            T.dir_bits = ix->dir_bits[j];
+            uint32_t *ids = nullptr;
+            if ((e = ix->alloc((void **)&ids, n * 4)) != hipSuccess) { st = from_hip(e); break; }
+            uint32_t *keys = (uint32_t *)tk1.ptr, *keys2 = (uint32_t *)tk2.ptr, *ids2 = (uint32_t *)ti2.ptr;
+            uint32_t *ids_cur = ids;
+            e = mih::extract_keys(codes, n, W, T.start, T.len, keys, ids_cur, s);
+            if (e == hipSuccess)
+                e = mih::radix_sort_pairs(keys, ids_cur, keys2, ids2, n, T.len, (uint32_t *)tmp.ptr, s);
+            if (e == hipSuccess && ids_cur != ids)
+                e = hipMemcpyAsync(ids, ids_cur, n * 4, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) { st = from_hip(e); break; }
+            T.ids = ids;
+            if (ix->table_mode == MIH_TABLE_DIRECT) {
+                uint32_t *off = nullptr;
+                const uint64_t nb = 1ull << T.len;
+                if ((e = ix->alloc((void **)&off, (nb + 1) * 4)) != hipSuccess) { st = from_hip(e); break; }
+                e = mih::bucket_offsets(keys, n, 0, off, nb, (uint32_t *)tmp.ptr, s);
+                T.off = off;
+            } else {
+                uint32_t *skeys = nullptr, *dir = nullptr;
+                const uint64_t nb = 1ull << T.dir_bits;
+                if ((e = ix->alloc((void **)&skeys, n * 4)) != hipSuccess ||
+                    (e = ix->alloc((void **)&dir, (nb + 1) * 4)) != hipSuccess) { st = from_hip(e); break; }
+                e = hipMemcpyAsync(skeys, keys, n * 4, hipMemcpyDeviceToDevice, s);
+                if (e == hipSuccess)
+                    e = mih::bucket_offsets(keys, n, T.len - T.dir_bits, dir, nb, (uint32_t *)tmp.ptr, s);
+                T.keys = skeys;
+                T.dir = dir;
+            }
+            if (e != hipSuccess) { st = from_hip(e); break; }
+            if (ix->codes_mode == MIH_CODES_INLINE) {
+                uint64_t *tc = nullptr;
+                if ((e = ix->alloc((void **)&tc, n * 8 * W)) != hipSuccess) { st = from_hip(e); break; }
+                if ((e = mih::gather_codes(codes, ids, n, W, tc, s)) != hipSuccess) { st = from_hip(e); break; }
+                T.codes = tc;
+            }
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) { st = from_hip(e); break; }
+        }
+        if (st != MIH_OK) break;
+        if ((e = ix->alloc((void **)&ix->tables_dev, sizeof(TableDev) * m)) != hipSuccess) { st = from_hip(e); break; }
+        if ((e = upload(ix->tables_dev, ix->tables_host, sizeof(TableDev) * m, s)) != hipSuccess) { st = from_hip(e); break; }
+    } while (0);
+    (void)hipStreamSynchronize(s);
+    tk1.release();
+    tk2.release();
+    ti2.release();
+    tmp.release();
+    if (st != MIH_OK) { delete ix; return st; }
+    ix->build_ms = ms_since(t0);
+    *out = ix;
+    return MIH_OK;
+}
+
+mih_status mih_knn_ex(const mih_index *cidx, const uint64_t *queries, uint32_t nq, uint32_t k,
+                      const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
+                      void *stream, mih_query_stats *stats)
+{
+    auto t0 = clk::now();
+    if (!cidx) return MIH_ERR_INVALID;
+    mih_index *ix = const_cast<mih_index *>(cidx);
+    MIH_TRY_STATUS(check_query_args(ix->bits, queries, nq, out_ids, out_dists));
+    if (!k_per_query && k > MIH_K_MAX) return MIH_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(ix->mu);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    BatchSpec b;
+    b.queries = queries;
+    b.nq = nq;
+    MIH_TRY_STATUS(read_k(nq, k, k_per_query, s, b.k));
+    row_offsets(b.k, b.row_off);
+    b.cap.resize(nq);
+    for (uint32_t i = 0; i < nq; ++i) b.cap[i] = mih_cap(b.k[i]);
+    mih_status st = mih_batch(ix, b, out_ids, out_dists, s, ix->scratch, 0, stats);
+    (void)hipStreamSynchronize(s);
+    if (stats) stats->elapsed_ms = ms_since(t0);
+    return st;
+}
+
+mih_status mih_knn(const mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
+                   const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists, void *stream)
+{
+    return mih_knn_ex(idx, queries, nq, k, k_per_query, out_ids, out_dists, stream, nullptr);
+}
+
+void mih_free(mih_index *idx) { delete idx; }
+
+mih_status mih_index_get_info(const mih_index *idx, mih_index_info *info)
+{
+    if (!idx || !info) return MIH_ERR_INVALID;
+    std::memset(info, 0, sizeof(*info));
+    info->n = idx->n;
+    info->bits = idx->bits;
+    info->m = idx->m;
+    info->table_mode = idx->table_mode;
+    info->codes_mode = idx->codes_mode;
+    for (uint32_t j = 0; j < idx->m; ++j) {
+        info->sub_len[j] = idx->len[j];
+        info->sub_start[j] = idx->start[j];
+        info->dir_bits[j] = idx->table_mode == MIH_TABLE_SORTED ? idx->dir_bits[j] : 0;
+    }
+    info->device_bytes = idx->device_bytes;
+    info->build_ms = idx->build_ms;
+    return MIH_OK;
+}
+
+mih_status mih_index_table(const mih_index *idx, uint32_t j, mih_table_view *view)
+{
+    if (!idx || !view || j >= idx->m) return MIH_ERR_INVALID;
+    const TableDev &T = idx->tables_host[j];
+    view->offsets = T.off;
+    view->keys = T.keys;
+    view->dir = T.dir;
+    view->ids = T.ids;
+    view->codes = T.codes;
+    view->len = T.len;
+    view->start = T.start;
+    view->dir_bits = idx->table_mode == MIH_TABLE_SORTED ? T.dir_bits : 0;
+    return MIH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,418 @@
+// Multi-index kNN search (Algorithm 3) for a batch of queries on the device.
+//
+// Search order.  Query g advances through steps t = 0, 1, 2, ...; step t
+// uses table a = t mod m and substring radius r' = floor(t/m) and looks up
+// every bucket of table a whose value differs from g's substring in exactly
+// r' bits (C(s_a, r') buckets, Eq. 1).  After steps 0..t every code within
+// Hamming distance t of g has been found (Proposition 2), so the query is
+// finished once the codes found within distance t number at least k; with
+// the bound tau of the candidate buffer this is the test tau <= t.
+//
+// De-duplication without per-query state.  A code h with substring distances
+// d_0..d_{m-1} is met at every step (r', a) with d_a = r'.  Steps are visited
+// in increasing t = m r' + a, so its first encounter is t_h = min_j (m d_j + j).
+// A candidate met at step (r', a) is accepted only if no table j gives an
+// earlier step: d_j > r' for j < a and d_j >= r' for j > a.  This keeps
+// exactly the codes the paper's per-query bitstring would keep (Section 6,
+// duplicate candidates), with no bitstring to clear.
+//
+// Scheduling.  All queries of a call advance in rounds; a round performs one
+// step of every active query.  The buckets of a step are enumerated in
+// colexicographic order of the flip masks and split into work items of
+// `chunk` masks; a persistent kernel hands items to waves through an atomic
+// counter.  A step that fits in one item is processed by one wave, which
+// then carries on with the query's next steps while they remain that small
+// (the wave alone owns the query, so it can test termination itself).
+// Between rounds a small kernel tests termination, moves unfinished queries
+// to their next non-empty step and regroups the active queries by step.
+#include "mih_common.h"
+#include "mih_query.h"
+
+namespace {
+
+constexpr int kJ = 8;                       // masks per lane per iteration
+constexpr uint32_t kWaves = MIH_BLOCK / MIH_WAVE;
+constexpr uint32_t kStage = MIH_WAVE * kJ;  // buckets staged per wave
+
+__device__ __forceinline__ uint32_t binom_calc(uint32_t n, uint32_t r)
+{
+    if (r > n) return 0;
+    uint64_t c = 1;
+    for (uint32_t i = 1; i <= r; ++i) c = c * (n - r + i) / i;
+    return (uint32_t)c;
+}
+
+// Colex unranking: the mask with `rho` set bits among s whose rank in
+// increasing numeric order is `rank` (combinatorial number system).
+__device__ __forceinline__ uint32_t unrank_mask(uint32_t rank, uint32_t rho, uint32_t s,
+                                                const uint32_t (*binom)[MIH_BINOM_N])
+{
+    uint32_t mask = 0;
+    int c = (int)s - 1;
+    for (int i = (int)rho; i >= 1; --i) {
+        while (c >= i && binom[c][i] > rank) --c;
+        rank -= binom[c][i];
+        mask |= 1u << c;
+        --c;
+    }
+    return mask;
+}
+
+// Next larger integer with the same number of set bits (Gosper).
+__device__ __forceinline__ uint32_t next_mask(uint32_t x)
+{
+    uint64_t v = x;
+    uint64_t c = v & (~v + 1);
+    uint64_t r = v + c;
+    return (uint32_t)((((r ^ v) >> 2) >> __builtin_ctzll(c)) | r);
+}
+
+template <int W>
+__device__ __forceinline__ uint64_t u64_uniform(uint64_t x)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+struct WaveStats {
+    uint64_t probes, candidates;
+};
+
+// One step of query q, masks of rank [rb, re) of shell (t mod m, t / m).
+template <int W, bool SORTED, bool INLINE>
+__device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t rb, uint32_t re,
+                             const uint32_t (*binom)[MIH_BINOM_N], uint32_t *stage_pos,
+                             uint32_t *stage_cum, WaveStats &ws)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t m = A.m;
+    const uint32_t rp = t / m, a = t - rp * m;
+    const TableDev T = A.tables[a];
+    const uint32_t s = T.len;
+    uint64_t g[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) g[w] = u64_uniform<W>(A.qb.queries[(uint64_t)q * W + w]);
+    const uint32_t key_q = substring<W>(g, T.start, s);
+    uint32_t tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
+
+    for (uint32_t base = rb; base < re; base += kStage) {
+        const uint32_t r0 = base + lane * kJ;
+        const uint32_t nmy = r0 < re ? (re - r0 < (uint32_t)kJ ? re - r0 : (uint32_t)kJ) : 0u;
+        uint32_t lo[kJ], cnt[kJ];
+        uint32_t mask = nmy ? unrank_mask(r0, rp, s, binom) : 0u;
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            cnt[j] = 0;
+            lo[j] = 0;
+            if ((uint32_t)j < nmy) {
+                const uint32_t key = key_q ^ mask;
+                if (!SORTED) {
+                    const uint32_t b0 = T.off[key];
+                    const uint32_t b1 = T.off[(uint64_t)key + 1];
+                    lo[j] = b0;
+                    cnt[j] = b1 - b0;
+                } else {
+                    const uint32_t cell = key >> (s - T.dir_bits);
+                    uint32_t x0 = T.dir[cell], x1 = T.dir[(uint64_t)cell + 1];
+                    // first position with keys >= key, then first with keys > key
+                    uint32_t l = x0, h = x1;
+                    while (l < h) {
+                        uint32_t mid = l + ((h - l) >> 1);
+                        if (T.keys[mid] < key) l = mid + 1; else h = mid;
+                    }
+                    uint32_t e = l;
+                    h = x1;
+                    while (e < h) {
+                        uint32_t mid = e + ((h - e) >> 1);
+                        if (T.keys[mid] <= key) e = mid + 1; else h = mid;
+                    }
+                    lo[j] = l;
+                    cnt[j] = e - l;
+                }
+                if ((uint32_t)j + 1 < nmy && rp > 0) mask = next_mask(mask);
+            }
+        }
+        // stage the non-empty buckets of the wave with the running count of
+        // candidates before each, then walk the candidates 64 at a time
+        uint32_t ne = 0, tc = 0;
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) { ne += cnt[j] ? 1u : 0u; tc += cnt[j]; }
+        const uint32_t ne_incl = wave_inclusive_sum(ne);
+        const uint32_t tc_incl = wave_inclusive_sum(tc);
+        const uint32_t NE = __shfl(ne_incl, MIH_WAVE - 1, MIH_WAVE);
+        const uint32_t TC = __shfl(tc_incl, MIH_WAVE - 1, MIH_WAVE);
+        uint32_t p = ne_incl - ne, c = tc_incl - tc;
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            if (cnt[j]) {
+                stage_pos[p] = lo[j];
+                stage_cum[p] = c;
+                ++p;
+                c += cnt[j];
+            }
+        }
+        wave_lds_sync();
+        ws.probes += __shfl(wave_inclusive_sum(nmy), MIH_WAVE - 1, MIH_WAVE);
+        ws.candidates += TC;
+
+        for (uint32_t e0 = 0; e0 < TC; e0 += MIH_WAVE) {
+            const uint32_t e = e0 + lane;
+            const bool live = e < TC;
+            uint32_t bl = 0, bh = NE;
+            while (bh - bl > 1) {
+                uint32_t mid = (bl + bh) >> 1;
+                if (stage_cum[mid] <= e) bl = mid; else bh = mid;
+            }
+            const uint32_t pos = live ? stage_pos[bl] + (e - stage_cum[bl]) : 0u;
+            uint64_t code[W];
+            uint32_t id = 0;
+            if (live) {
+                if (INLINE) {
+                    load_code<W>(T.codes + (uint64_t)pos * W, code);
+                } else {
+                    id = T.ids[pos];
+                    load_code<W>(A.codes + (uint64_t)id * W, code);
+                }
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w) code[w] = g[w];
+            }
+            const uint32_t d = hamming<W>(code, g);
+            bool keep = live && d <= tau;
+            if (keep) {
+                uint64_t x[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) x[w] = code[w] ^ g[w];
+                for (uint32_t j = 0; j < m; ++j) {
+                    if (j == a) continue;
+                    const uint32_t dj = __popc(substring<W>(x, A.tables[j].start, A.tables[j].len));
+                    if (j < a ? dj <= rp : dj < rp) { keep = false; break; }
+                }
+                if (keep && INLINE) id = T.ids[pos];
+            }
+            append_candidates(A.qb, q, keep, d, id);
+            if (__ballot(keep)) tau = tighten_tau(A.qb, q, tau);
+        }
+        wave_lds_sync();
+        const uint32_t g_tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
+        tau = g_tau < tau ? g_tau : tau;
+    }
+}
+
+template <int W, bool SORTED, bool INLINE>
+__global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
+{
+    __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
+    __shared__ uint32_t stage_pos[kWaves][kStage];
+    __shared__ uint32_t stage_cum[kWaves][kStage];
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += MIH_BLOCK)
+        binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
+    __syncthreads();
+
+    const uint32_t n_groups = A.ctrl->n_groups;
+    const uint64_t total = A.ctrl->total_items;
+    const uint32_t chunk = A.chunk;
+    WaveStats ws = {0, 0};
+    for (;;) {
+        uint64_t item = 0;
+        if (lane == 0) item = atomicAdd(A.work, 1ull);
+        item = u64_uniform<1>(__shfl(item, 0, MIH_WAVE));
+        if (item >= total) break;
+        // group of the item: the last group whose first item is <= item
+        uint32_t gl = 0, gh = n_groups;
+        while (gh - gl > 1) {
+            uint32_t mid = (gl + gh) >> 1;
+            if (A.groups[mid].item_start <= item) gl = mid; else gh = mid;
+        }
+        const mih::Group G = A.groups[gl];
+        const uint64_t rel = item - G.item_start;
+        const uint32_t slot = G.slot_start + (uint32_t)(rel / G.ipq);
+        const uint32_t part = (uint32_t)(rel % G.ipq);
+        const uint32_t q = A.active[slot];
+        uint32_t t = G.t;
+        const uint32_t rp = t / A.m;
+        const uint32_t M = binom_calc(A.tables[t - rp * A.m].len, rp);
+        const uint32_t rb = part * chunk;
+        const uint32_t re = rb + chunk < M ? rb + chunk : M;
+        process_step<W, SORTED, INLINE>(A, q, t, rb, re, binom, stage_pos[wave], stage_cum[wave], ws);
+        if (G.ipq != 1) continue;
+        // the whole step belonged to this wave: keep going while steps are small
+        for (;;) {
+            const uint32_t tau = tighten_tau(A.qb, q, __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q)));
+            if (tau <= t || t >= A.t_all) break;
+            const uint32_t tn = t + 1;
+            const uint32_t rpn = tn / A.m;
+            const uint32_t Mn = binom_calc(A.tables[tn - rpn * A.m].len, rpn);
+            if (Mn > chunk) break;
+            if (Mn) process_step<W, SORTED, INLINE>(A, q, tn, 0, Mn, binom, stage_pos[wave],
+                                                    stage_cum[wave], ws);
+            t = tn;
+            if (lane == 0) A.t[q] = t;
+        }
+    }
+    if (lane == 0) {
+        atomicAdd(&A.stats[0], (unsigned long long)ws.probes);
+        atomicAdd(&A.stats[1], (unsigned long long)ws.candidates);
+    }
+}
+
+// Termination test after the last processed step and move to the next
+// non-empty step (a shell is empty when r' exceeds the substring length).
+__global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A, uint32_t *next_t)
+{
+    const uint32_t slot = blockIdx.x * MIH_BLOCK + threadIdx.x;
+    if (slot >= A.ctrl->n_active) return;
+    const uint32_t q = A.active[slot];
+    const uint32_t nb = A.qb.bits + 1;
+    const uint32_t *h = A.qb.hist + (uint64_t)q * nb;
+    const uint32_t k = A.qb.k[q];
+    uint32_t D = 0xFFFFFFFFu, cum = 0;
+    for (uint32_t d = 0; d < nb; ++d) {
+        cum += h[d];
+        if (cum >= k) { D = d; break; }
+    }
+    if (D != 0xFFFFFFFFu && D < A.qb.tau[q]) A.qb.tau[q] = D;
+    uint32_t t = A.t[q];
+    uint32_t out = 0xFFFFFFFFu;
+    if (!(D <= t || t >= A.t_all)) {
+        for (uint32_t tn = t + 1;; ++tn) {
+            const uint32_t rp = tn / A.m;
+            if (binom_calc(A.tables[tn - rp * A.m].len, rp) > 0) { out = tn; break; }
+            if (D <= tn || tn >= A.t_all) break;
+        }
+    }
+    if (out != 0xFFFFFFFFu) A.t[q] = out;
+    next_t[slot] = out;
+}
+
+// Regroup the surviving queries by their next step (one workgroup).
+__global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A, const uint32_t *next_t,
+                                                           uint32_t *new_active, mih::Group *groups,
+                                                           mih::Control *ctrl_out)
+{
+    extern __shared__ uint32_t bins[];   // [nbins] counts, then [nbins] cursors
+    __shared__ uint32_t s_active, s_groups;
+    __shared__ unsigned long long s_items;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nbins = A.t_all + 1;
+    const uint32_t n_old = A.ctrl->n_active;
+    for (uint32_t i = tid; i < 2 * nbins; i += 1024) bins[i] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n_old; i += 1024) {
+        uint32_t nt = next_t[i];
+        if (nt != 0xFFFFFFFFu) atomicAdd(&bins[nt], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t slot = 0, ng = 0;
+        uint64_t items = 0;
+        for (uint32_t b = 0; b < nbins; ++b) {
+            uint32_t c = bins[b];
+            bins[nbins + b] = slot;
+            if (!c) continue;
+            const uint32_t rp = b / A.m;
+            const uint32_t M = binom_calc(A.tables[b - rp * A.m].len, rp);
+            const uint32_t ipq = (M + A.chunk - 1) / A.chunk;
+            mih::Group G;
+            G.t = b;
+            G.count = c;
+            G.ipq = ipq;
+            G.slot_start = slot;
+            G.item_start = items;
+            groups[ng++] = G;
+            slot += c;
+            items += (uint64_t)c * ipq;
+        }
+        s_active = slot;
+        s_groups = ng;
+        s_items = items;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n_old; i += 1024) {
+        uint32_t nt = next_t[i];
+        if (nt != 0xFFFFFFFFu) new_active[atomicAdd(&bins[nbins + nt], 1u)] = A.active[i];
+    }
+    if (tid == 0) {
+        ctrl_out->n_active = s_active;
+        ctrl_out->n_groups = s_groups;
+        ctrl_out->total_items = s_items;
+        *A.work = 0;
+    }
+}
+
+template <int W, bool SORTED, bool INLINE>
+hipError_t launch_round_t(const mih::MihArgs &A, uint32_t grid, hipStream_t s)
+{
+    mih_round_kernel<W, SORTED, INLINE><<<grid, MIH_BLOCK, 0, s>>>(A);
+    return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_round_w(const mih::MihArgs &A, uint32_t grid, hipStream_t s)
+{
+    if (A.sorted) {
+        if (A.inline_codes) return launch_round_t<W, true, true>(A, grid, s);
+        return launch_round_t<W, true, false>(A, grid, s);
+    }
+    if (A.inline_codes) return launch_round_t<W, false, true>(A, grid, s);
+    return launch_round_t<W, false, false>(A, grid, s);
+}
+
+template <int W, bool SORTED, bool INLINE>
+int occupancy_t()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, mih_round_kernel<W, SORTED, INLINE>,
+                                                     MIH_BLOCK, 0) != hipSuccess)
+        return 1;
+    return blocks > 0 ? blocks : 1;
+}
+
+}  // namespace
+
+namespace mih {
+
+hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s)
+{
+    switch (A.W) {
+    case 1: return launch_round_w<1>(A, grid, s);
+    case 2: return launch_round_w<2>(A, grid, s);
+    case 3: return launch_round_w<3>(A, grid, s);
+    case 4: return launch_round_w<4>(A, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int mih_round_occupancy(uint32_t W, bool sorted, bool inline_codes)
+{
+#define MIH_OCC(w)                                                        \
+    case w:                                                               \
+        if (sorted) return inline_codes ? occupancy_t<w, true, true>()    \
+                                        : occupancy_t<w, true, false>();  \
+        return inline_codes ? occupancy_t<w, false, true>()               \
+                            : occupancy_t<w, false, false>();
+    switch (W) {
+        MIH_OCC(1)
+        MIH_OCC(2)
+        MIH_OCC(3)
+        MIH_OCC(4)
+    default: return 1;
+    }
+#undef MIH_OCC
+}
+
+hipError_t mih_advance(const MihArgs &A, uint32_t nq, uint32_t *next_t, uint32_t *new_active,
+                       Group *groups, Control *ctrl_out, hipStream_t s)
+{
+    if (nq == 0) return hipSuccess;
+    mih_advance_kernel<<<(nq + MIH_BLOCK - 1) / MIH_BLOCK, MIH_BLOCK, 0, s>>>(A, next_t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = sizeof(uint32_t) * 2 * (A.t_all + 1);
+    mih_regroup_kernel<<<1, 1024, lds, s>>>(A, next_t, new_active, groups, ctrl_out);
+    return hipGetLastError();
+}
+
+}  // namespace mih
