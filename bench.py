@@ -1,0 +1,285 @@
+#!/usr/bin/env python3
+"""Exact Hamming kNN throughput on one MI355X: multi-index hashing vs the GPU
+linear scan, on synthetic codes shaped like the paper's 1B-code experiments.
+
+Default workload: 1e9 uniform 64-bit codes (seed 0), m = 2 substrings of 32
+bits, 10,000 queries (seed 1), k = 100.  A step is one mih_knn call over the
+whole query batch (tables already built, codes and queries resident in HBM).
+Prints one JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--config 1..4] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "exact kNN queries/s, MIH vs GPU linear scan, 1B×64b k=100; p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit integer vector lane-ops per second
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def log(msg: str):
+    sys.stderr.write(f"[bench {time.strftime('%H:%M:%S')}] {msg}\n")
+    sys.stderr.flush()
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4])
+    ap.add_argument("--n", type=int, default=None, help="override the database size")
+    ap.add_argument("--nq", type=int, default=None, help="override the number of queries")
+    ap.add_argument("--k", type=int, default=None, help="override k (single value)")
+    ap.add_argument("--m", type=int, default=None, help="override the number of substrings")
+    ap.add_argument("--table-mode", default="auto", choices=["auto", "direct", "sorted"])
+    ap.add_argument("--codes-mode", default="auto", choices=["auto", "inline", "indirect"])
+    ap.add_argument("--linscan-steps", type=int, default=None)
+    ap.add_argument("--no-linscan", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="wall-time budget of the CPU oracle sample")
+    ap.add_argument("--threads", type=int, default=None, help="host threads for generation/oracle")
+    ap.add_argument("--copy-calib", type=float, default=0.0,
+                    help="also run one plain device copy of this many GiB (counter calibration)")
+    return ap.parse_args()
+
+
+def workload(args):
+    import datagen
+    cfg = dict(datagen.CONFIGS[args.config])
+    if args.n is not None:
+        cfg["n"] = args.n
+    if args.nq is not None:
+        cfg["nq"] = args.nq
+    if args.m is not None:
+        cfg["m"] = args.m
+    if args.k is not None:
+        cfg["ks"] = (args.k,)
+    return cfg
+
+
+def to_device(codes: np.ndarray, chunk_rows: int = 1 << 24):
+    """Copy host codes to a device int64 tensor through a pinned staging buffer."""
+    import torch
+    n, W = codes.shape
+    dev = torch.empty((n, W), dtype=torch.int64, device="cuda")
+    if n == 0:
+        return dev
+    rows = min(chunk_rows, n)
+    pinned = torch.empty((rows, W), dtype=torch.int64, pin_memory=True)
+    src = codes.view(np.int64)
+    for lo in range(0, n, rows):
+        hi = min(n, lo + rows)
+        pinned[: hi - lo].copy_(torch.from_numpy(src[lo:hi]))
+        dev[lo:hi].copy_(pinned[: hi - lo], non_blocking=True)
+        torch.cuda.synchronize()
+    return dev
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path: run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import datagen
+    import paper_1307_2982_amd as mih
+
+    mih.load()   # fails loudly if libmih.so is missing
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    threads = args.threads or max(1, min(os.cpu_count() or 1, 16))
+    cfg = workload(args)
+    n, bits, m, nq = cfg["n"], cfg["bits"], cfg["m"], cfg["nq"]
+    W = bits // 64
+    kind = cfg["kind"]
+    ks = cfg["ks"]
+    mixed_k = len(ks) > 1
+    log(f"workload {cfg['name']}: n={n} bits={bits} m={m} nq={nq} k={ks} threads={threads}")
+
+    t0 = time.time()
+    codes = datagen.db_codes(kind, n, bits, threads=threads)
+    queries = datagen.query_codes(kind, nq, bits, threads=threads)
+    if mixed_k:
+        kq = datagen.choice_u32(nq, ks, datagen.SEED_K)
+        k_arg = kq.tolist()
+        k_list = kq
+    else:
+        k_arg = int(ks[0])
+        k_list = np.full(nq, ks[0], dtype=np.uint32)
+    log(f"generated codes on the host in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    dc = to_device(codes)
+    dq = to_device(queries)
+    log(f"copied to the device in {time.time() - t0:.1f}s")
+
+    t0 = time.time()
+    idx = mih.build(dc, m, table_mode=args.table_mode, codes_mode=args.codes_mode)
+    torch.cuda.synchronize()
+    info = idx.info()
+    log(f"built index in {time.time() - t0:.2f}s ({info['table_mode']}/{info['codes_mode']}, "
+        f"{info['device_bytes'] / 2**30:.1f} GiB)")
+
+    if args.copy_calib > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the counter readings of the search kernel
+        words = int(args.copy_calib * 2**30) // 8
+        a = torch.ones(words, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {words * 8} bytes read and written")
+        del a, b
+
+    # ---------------- multi-index hashing
+    for _ in range(args.warmup):
+        idx.knn(dq, k_arg)
+    torch.cuda.synchronize()
+    step_ms, stats = [], []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ids, dists, st = idx.knn(dq, k_arg, stats=True)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t) * 1e3)
+        stats.append(st)
+    mih_ms = float(np.mean(step_ms))
+    mih_qps = nq / (mih_ms / 1e3)
+    log(f"MIH: {mih_ms:.1f} ms/step -> {mih_qps:,.0f} queries/s; last step {stats[-1]}")
+
+    # ---------------- roofline of the search kernel
+    st = stats[-1]
+    if info["codes_mode"] == "inline":
+        per_cand = 8 * W
+    else:
+        per_cand = 4 + 8 * W
+    per_probe = 8 if info["table_mode"] == "direct" else 12
+    alg_bytes = st["probes"] * per_probe + st["candidates"] * per_cand + st["appended"] * 16
+    kern_ms = st["search_kernel_ms"]
+    launches = max(1, st["search_launches"])
+    achieved = alg_bytes / (kern_ms / 1e3) / 1e9 if kern_ms > 0 else 0.0
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": "mih_round_kernel", "launches_per_step": launches,
+        "avg_launch_ms": round(kern_ms / launches, 3),
+        "alg_bytes_per_step": int(alg_bytes),
+        "per_unit": {"probe_B": per_probe, "candidate_B": per_cand, "appended_B": 16},
+        "probes_per_query": st["probes"] / nq, "candidates_per_query": st["candidates"] / nq,
+    }
+
+    # ---------------- linear scan
+    lin = None
+    if not args.no_linscan:
+        lsteps = args.linscan_steps if args.linscan_steps is not None else args.steps
+        li, ld = mih.linscan_knn(dc, dq, k_arg)
+        torch.cuda.synchronize()
+        parity_mih_vs_linscan = bool(torch.equal(li, ids) and torch.equal(ld, dists))
+        lms, lst = [], None
+        for _ in range(max(1, lsteps)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            li, ld, lst = mih.linscan_knn(dc, dq, k_arg, stats=True)
+            torch.cuda.synchronize()
+            lms.append((time.perf_counter() - t) * 1e3)
+        lin_ms = float(np.mean(lms))
+        lin_qps = nq / (lin_ms / 1e3)
+        ops = lst["pairs"] * 4 * W   # per 64-bit word: 2 xor + 2 bit counts (32-bit lanes)
+        scan_ms = lst["scan_kernel_ms"]
+        achieved_ops = ops / (scan_ms / 1e3) / 1e12 if scan_ms > 0 else 0.0
+        lin = {
+            "value": round(lin_qps, 1), "unit": "queries/s", "ms_per_step": round(lin_ms, 2),
+            "steps": len(lms), "speedup_mih_over_linscan": round(mih_qps / lin_qps, 2),
+            "parity_with_mih": parity_mih_vs_linscan,
+            "roofline": {"bound": "alu", "achieved": round(achieved_ops, 2), "peak": round(VALU_PEAK_TOPS, 1),
+                         "unit": "Tops/s", "frac": round(achieved_ops / VALU_PEAK_TOPS, 4),
+                         "kernel": "linscan_kernel", "ops_per_pair": 4 * W,
+                         "kernel_ms": round(scan_ms, 2), "sample_kernel_ms": round(lst["sample_kernel_ms"], 2)},
+            "appended_per_query": lst["appended"] / nq, "reruns": lst["reruns"],
+        }
+        log(f"linscan: {lin_ms:.1f} ms/step -> {lin_qps:,.0f} queries/s; parity with MIH: "
+            f"{parity_mih_vs_linscan}; kernel {scan_ms:.1f} ms = {achieved_ops:.2f} Tops/s")
+
+    # ---------------- CPU oracle: bounded sample, also a full-size parity check
+    cpu = None
+    parity_oracle = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        gi = ids.reshape(-1).cpu().numpy().view(np.uint32)
+        gd = dists.reshape(-1).cpu().numpy().view(np.uint32)
+        off = np.concatenate([[0], np.cumsum(k_list.astype(np.int64))])
+        rng = np.random.default_rng(123)
+        order = rng.permutation(nq)
+        done, spent, ok = 0, 0.0, True
+        while done < nq and spent < args.cpu_seconds:
+            sel = order[done: done + threads]
+            t = time.perf_counter()
+            oi, od = oracle.knn(codes, queries[sel], k_list[sel], threads=threads)
+            spent += time.perf_counter() - t
+            used = oracle.knn.last_threads
+            o = 0
+            for q in sel:
+                kq_ = int(k_list[q])
+                ok &= bool(np.array_equal(oi[o:o + kq_], gi[off[q]:off[q + 1]]) and
+                           np.array_equal(od[o:o + kq_], gd[off[q]:off[q + 1]]))
+                o += kq_
+            done += len(sel)
+        cpu = {"value": round(done / spent, 3), "unit": "queries/s", "cores": int(used),
+               "kind": "oracle",
+               "sample": f"{done} of the {nq} queries (seeded random subset) against all {n} codes, "
+                         f"same k; {spent:.1f} s wall on {used} host threads"}
+        parity_oracle = {"queries_checked": done, "bit_exact": ok}
+        log(f"oracle: {done} queries in {spent:.1f}s on {used} threads; MIH == oracle: {ok}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(mih_qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mih_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": cfg["name"] + (f", {nq} queries, k={ks[0]}" if not mixed_k else
+                                       f", {nq} queries, k drawn from {list(ks)}"),
+            "n": n, "bits": bits, "m": m, "nq": nq, "k": list(ks),
+            "table_mode": info["table_mode"], "codes_mode": info["codes_mode"],
+            "index_GiB": round(info["device_bytes"] / 2**30, 2), "build_ms": round(info["build_ms"], 1),
+        },
+        "roofline": roofline,
+        "linscan": lin,
+        "cpu_baseline": cpu,
+        "parity": {"mih_vs_oracle_sample": parity_oracle,
+                   "mih_vs_linscan_all": lin["parity_with_mih"] if lin else None},
+        "mih_step_ms": [round(x, 2) for x in step_ms],
+        "mih_stats": {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in stats[-1].items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
