@@ -88,6 +88,27 @@ def to_device(codes: np.ndarray, chunk_rows: int = 1 << 24):
     return dev
 
 
+def counter_traffic(kernel_sources, counters_file):
+    """HBM bytes per launch of the search kernel from committed rocprofv3
+    counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a
+    plain copy of known size), or None when the kernel source has changed
+    since the counters were taken or no counters exist for this workload."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", counters_file)
+    if not os.path.exists(path):
+        return None, None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest()[:16] != rec["source_sha256_16"]:
+        return None, rec
+    cal = rec["copy_calibration"]
+    fetch = np.mean(rec["fetch_kib_per_launch"]) * cal["fetch_factor"]
+    write = np.mean(rec["write_kib_per_launch"]) * cal["write_factor"]
+    return float((fetch + write) * 1024.0), rec
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
 
@@ -176,9 +197,16 @@ def main():
     kern_ms = st["search_kernel_ms"]
     launches = max(1, st["search_launches"])
     achieved = alg_bytes / (kern_ms / 1e3) / 1e9 if kern_ms > 0 else 0.0
+    traffic = None
+    if (n, bits, m, nq, tuple(ks)) == (1_000_000_000, 64, 2, 10_000, (100,)) and \
+            (info["table_mode"], info["codes_mode"]) == ("direct", "inline"):
+        traffic, _ = counter_traffic(None, "mih_round_kernel_1e9x64_m2_k100_counters.json")
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": round(traffic) if traffic is not None else None,
+        "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "alg_bytes_per_launch": int(alg_bytes / launches),
         "kernel": "mih_round_kernel", "launches_per_step": launches,
         "avg_launch_ms": round(kern_ms / launches, 3),
         "alg_bytes_per_step": int(alg_bytes),
