@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="wall-time budget of the CPU oracle sample")
     ap.add_argument("--threads", type=int, default=None, help="host threads for generation/oracle")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time the search over a grid of launch tunings")
+    ap.add_argument("--m-sweep", default="",
+                    help="comma-separated extra m values to build and time (e.g. 3,4)")
     ap.add_argument("--copy-calib", type=float, default=0.0,
                     help="also run one plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
@@ -214,6 +218,51 @@ def main():
         "probes_per_query": st["probes"] / nq, "candidates_per_query": st["candidates"] / nq,
     }
 
+    # ---------------- launch tunings (speed only; results must not change)
+    sweep = None
+    if args.sweep:
+        base_t = idx.get_tuning()
+        sweep = []
+        for J in (4, 8, 16):
+            for chunk in (64 * J * 2, 64 * J * 8, 64 * J * 32):
+                for bpc in (0, 2):
+                    idx.set_tuning(J, chunk, bpc)
+                    idx.knn(dq, k_arg)
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    si, sd, sst = idx.knn(dq, k_arg, stats=True)
+                    torch.cuda.synchronize()
+                    ms = (time.perf_counter() - t) * 1e3
+                    same = bool(torch.equal(si, ids) and torch.equal(sd, dists))
+                    sweep.append({"probes_per_lane": J, "chunk": chunk, "blocks_per_cu": bpc,
+                                  "ms": round(ms, 2), "kernel_ms": round(sst["search_kernel_ms"], 2),
+                                  "same_result": same})
+                    log(f"tuning J={J} chunk={chunk} bpc={bpc}: {ms:.1f} ms same={same}")
+        idx.set_tuning(base_t["probes_per_lane"], base_t["chunk"], base_t["blocks_per_cu"])
+
+    m_sweep = None
+    if args.m_sweep:
+        m_sweep = []
+        for mm in [int(x) for x in args.m_sweep.split(",") if x]:
+            ix2 = mih.build(dc, mm, table_mode=args.table_mode, codes_mode=args.codes_mode)
+            ix2.knn(dq, k_arg)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            si, sd, sst = ix2.knn(dq, k_arg, stats=True)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3
+            inf2 = ix2.info()
+            m_sweep.append({"m": mm, "ms": round(ms, 2), "queries_per_s": round(nq / (ms / 1e3), 1),
+                            "same_result": bool(torch.equal(si, ids) and torch.equal(sd, dists)),
+                            "probes_per_query": sst["probes"] / nq,
+                            "candidates_per_query": sst["candidates"] / nq,
+                            "table_mode": inf2["table_mode"], "codes_mode": inf2["codes_mode"],
+                            "index_GiB": round(inf2["device_bytes"] / 2**30, 2)})
+            log(f"m={mm}: {ms:.1f} ms -> {nq / (ms / 1e3):,.0f} q/s, same={m_sweep[-1]['same_result']}")
+            ix2.close()
+            del ix2
+            torch.cuda.synchronize()
+
     # ---------------- linear scan
     lin = None
     if not args.no_linscan:
@@ -304,6 +353,9 @@ def main():
         "parity": {"mih_vs_oracle_sample": parity_oracle,
                    "mih_vs_linscan_all": lin["parity_with_mih"] if lin else None},
         "mih_step_ms": [round(x, 2) for x in step_ms],
+        "tuning": idx.get_tuning(),
+        "tuning_sweep": sweep,
+        "m_sweep": m_sweep,
         "mih_stats": {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in stats[-1].items()},
     }
     print(json.dumps(out), flush=True)

@@ -189,6 +189,22 @@ void mih_free(mih_index *idx);
 /* Static, human-readable name of a status. */
 const char *mih_status_str(mih_status s);
 
+/* Launch parameters of the multi-index search.  They change speed only; the
+ * result of every query is the same for all of them. */
+typedef struct mih_tuning {
+    uint32_t probes_per_lane;  /* shell masks per lane per iteration: 4, 8 or 16 */
+    uint32_t chunk;            /* shell masks per work item: a multiple of
+                                  64 * probes_per_lane, at most 2^20           */
+    uint32_t blocks_per_cu;    /* persistent workgroups per CU, 0 = all that fit */
+} mih_tuning;
+
+/* Current tuning of an index (defaults after mih_build: 4, 8192, 0). */
+mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
+
+/* Replace the tuning; MIH_ERR_INVALID (index unchanged) if a field is out of
+ * range.  Not thread-safe with concurrent mih_knn calls on the same index. */
+mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning);
+
 /* Fill *info (host memory) with the index's shape and modes. */
 mih_status mih_index_get_info(const mih_index *idx, mih_index_info *info);
 

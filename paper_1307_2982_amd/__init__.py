@@ -74,8 +74,17 @@ class ScanStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("probes_per_lane", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 EXPORTED = ["mih_build", "mih_knn", "mih_knn_ex", "linscan_knn", "linscan_knn_ex", "mih_free",
-            "mih_status_str", "mih_index_get_info", "mih_index_table"]
+            "mih_status_str", "mih_index_get_info", "mih_index_table", "mih_get_tuning",
+            "mih_set_tuning"]
 
 _lib = None
 
@@ -112,6 +121,10 @@ def load():
     L.mih_index_get_info.restype = i32
     L.mih_index_table.argtypes = [vp, u32, ctypes.POINTER(TableView)]
     L.mih_index_table.restype = i32
+    L.mih_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.mih_get_tuning.restype = i32
+    L.mih_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.mih_set_tuning.restype = i32
     _lib = L
     return L
 
@@ -188,6 +201,15 @@ class Index:
                 "sub_len": list(inf.sub_len[:m]), "sub_start": list(inf.sub_start[:m]),
                 "dir_bits": list(inf.dir_bits[:m]), "device_bytes": inf.device_bytes,
                 "build_ms": inf.build_ms}
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(load().mih_get_tuning(self._h, ctypes.byref(t)), "mih_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, probes_per_lane: int, chunk: int, blocks_per_cu: int = 0):
+        t = Tuning(probes_per_lane, chunk, blocks_per_cu)
+        _check(load().mih_set_tuning(self._h, ctypes.byref(t)), "mih_set_tuning")
 
     def table(self, j: int) -> dict:
         """Copies of table j's device arrays (as CPU tensors), for inspection."""

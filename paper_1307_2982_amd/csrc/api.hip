@@ -163,7 +163,7 @@ void carve_batch(Carver &c, const BatchSpec &b, uint32_t bits, uint32_t W, uint6
 {
     const uint32_t nq = b.nq;
     B.qb.k = c.take<uint32_t>(nq);
-    B.qb.tau = c.take<uint32_t>(nq);
+    B.qb.tau = c.take<uint32_t>((uint64_t)nq + 16);   // the scan reads whole batches of 16
     B.qb.count = c.take<uint32_t>(nq);
     B.qb.cap = c.take<uint32_t>(nq);
     B.qb.buf_off = c.take<uint64_t>(nq);
@@ -248,7 +248,7 @@ struct mih_index {
     std::vector<void *> allocs;
     uint64_t device_bytes = 0;
     double build_ms = 0;
-    uint32_t chunk = 1024;
+    mih_tuning tuning = {4, 8192, 0};
     std::mutex mu;
     Scratch scratch, rerun_scratch;
     mih::Control *ctrl_host = nullptr;   // pinned
@@ -335,16 +335,23 @@ mih_status linscan_batch(const uint64_t *codes, uint64_t n, uint32_t bits, Batch
     std::vector<uint64_t> buf_off;
     const uint64_t words = buffer_words(b, buf_off);
     BatchBufs B;
+    const uint64_t qrows = mih::linscan_pad(b.nq);
     Carver c0;
     carve_batch(c0, b, bits, W, words, 1, B);
+    c0.take<uint64_t>(qrows * W);
     Scratch mem;
     MIH_TRY(mem.ensure(c0.used));
     Carver c;
     c.base = (char *)mem.ptr;
     carve_batch(c, b, bits, W, words, 1, B);
+    uint64_t *qpad = c.take<uint64_t>(qrows * W);
     mih_status st = MIH_OK;
     do {
-        hipError_t e = upload((void *)B.qb.k, b.k.data(), sizeof(uint32_t) * b.nq, s);
+        // the scan reads queries in whole batches: a zero-padded copy
+        hipError_t e = mih::fill_u64(qpad, qrows * W, 0ull, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(qpad, b.queries, sizeof(uint64_t) * W * b.nq, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = upload((void *)B.qb.k, b.k.data(), sizeof(uint32_t) * b.nq, s);
         if (e == hipSuccess) e = upload((void *)B.qb.cap, b.cap.data(), sizeof(uint32_t) * b.nq, s);
         if (e == hipSuccess) e = upload((void *)B.qb.buf_off, buf_off.data(), sizeof(uint64_t) * b.nq, s);
         if (e == hipSuccess) e = upload(B.row_off, b.row_off.data(), sizeof(uint64_t) * b.nq, s);
@@ -352,6 +359,7 @@ mih_status linscan_batch(const uint64_t *codes, uint64_t n, uint32_t bits, Batch
         L.codes = codes;
         L.n = n;
         L.qb = B.qb;
+        L.queries_padded = qpad;
         L.W = W;
         uint32_t kmax = 0;
         for (uint32_t v : b.k) kmax = std::max(kmax, v);
@@ -491,14 +499,17 @@ mih_status mih_batch(mih_index *ix, BatchSpec &b, uint32_t *out_ids, uint32_t *o
     A.t_all = ix->t_all;
     A.sorted = ix->table_mode == MIH_TABLE_SORTED;
     A.inline_codes = ix->codes_mode == MIH_CODES_INLINE;
-    A.chunk = ix->chunk;
+    A.chunk = ix->tuning.chunk;
+    A.J = ix->tuning.probes_per_lane;
     A.qb = B.qb;
     A.t = B.t;
     A.groups = B.groups;
     A.ctrl = B.ctrl;
     A.work = B.work;
     A.stats = B.stats;
-    const uint32_t grid = num_cus() * (uint32_t)mih::mih_round_occupancy(W, A.sorted, A.inline_codes);
+    uint32_t per_cu = (uint32_t)mih::mih_round_occupancy(W, A.sorted, A.inline_codes, A.J);
+    if (ix->tuning.blocks_per_cu && ix->tuning.blocks_per_cu < per_cu) per_cu = ix->tuning.blocks_per_cu;
+    const uint32_t grid = num_cus() * per_cu;
 
     uint32_t n_active = (uint32_t)active.size();
     uint32_t *cur = B.active0, *nxt = B.active1;
@@ -797,6 +808,26 @@ mih_status mih_index_get_info(const mih_index *idx, mih_index_info *info)
     }
     info->device_bytes = idx->device_bytes;
     info->build_ms = idx->build_ms;
+    return MIH_OK;
+}
+
+mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning)
+{
+    if (!idx || !tuning) return MIH_ERR_INVALID;
+    *tuning = idx->tuning;
+    return MIH_OK;
+}
+
+mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning)
+{
+    if (!idx || !tuning) return MIH_ERR_INVALID;
+    const uint32_t J = tuning->probes_per_lane;
+    if (!mih::mih_probes_per_lane_ok(J)) return MIH_ERR_INVALID;
+    if (tuning->chunk == 0 || tuning->chunk % (64 * J) != 0 || tuning->chunk > (1u << 20))
+        return MIH_ERR_INVALID;
+    if (tuning->blocks_per_cu > 64) return MIH_ERR_INVALID;
+    std::lock_guard<std::mutex> lock(idx->mu);
+    idx->tuning = *tuning;
     return MIH_OK;
 }
 

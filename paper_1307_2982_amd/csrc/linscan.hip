@@ -73,6 +73,23 @@ __global__ __launch_bounds__(MIH_BLOCK) void sample_bound_kernel(const uint64_t 
     }
 }
 
+// Bit count of x plus acc in one v_bcnt_u32_b32.  Written out because the
+// compiler otherwise regroups the additions and spends a separate add on the
+// bound.  acc_s is a wave-uniform value (scalar operand), acc_v a vector one.
+__device__ __forceinline__ uint32_t bcnt_acc_s(uint32_t x, uint32_t acc_s)
+{
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "s"(acc_s));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t bcnt_acc_v(uint32_t x, uint32_t acc_v)
+{
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc_v));
+    return r;
+}
+
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
 {
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
@@ -80,12 +97,15 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// queries and qb.tau hold nbatches * QB rows; rows from qb.nq on are padding
+// whose bound test is forced to fail.
 template <int W, int QB, int R>
 __global__ __launch_bounds__(MIH_BLOCK) void linscan_kernel(const uint64_t *__restrict__ codes,
+                                                            const uint64_t *__restrict__ queries,
                                                             uint64_t n, QueryBatch qb,
                                                             uint64_t range_len, uint32_t nbatches)
 {
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63;
     const uint64_t begin = (uint64_t)blockIdx.x * range_len;
     const uint64_t end = begin + range_len < n ? begin + range_len : n;
     // different workgroups start at different query batches, so that each
@@ -104,49 +124,61 @@ __global__ __launch_bounds__(MIH_BLOCK) void linscan_kernel(const uint64_t *__re
 #pragma unroll
             for (int w = 0; w < W; ++w) c[r][w] = codes[src * W + w];
         }
+        uint32_t b = rot;
+        // the bounds of a batch come in one vector load (lane j holds query
+        // q0 + j mod QB) issued one batch ahead
+        const uint32_t lq = lane % (uint32_t)QB;
+        uint32_t tv = load_relaxed(qb.tau + b * QB + lq);
         for (uint32_t bi = 0; bi < nbatches; ++bi) {
-            uint32_t b = bi + rot;
-            if (b >= nbatches) b -= nbatches;
             const uint32_t q0 = b * QB;
+            const uint32_t bn = b + 1 == nbatches ? 0u : b + 1;
+            const uint32_t tv_next = load_relaxed(qb.tau + bn * QB + lq);
+            const uint64_t *qp = queries + (uint64_t)q0 * W;
             uint64_t g[QB][W];
-            uint32_t tau[QB], bias[QB];
+            uint32_t bias[QB];   // 2^31 - 1 - tau, or 2^31 for padding rows
 #pragma unroll
             for (int j = 0; j < QB; ++j) {
-                const uint32_t q = q0 + j;
-                const bool ok = q < qb.nq;
-                const uint32_t qq = ok ? q : 0;
 #pragma unroll
-                for (int w = 0; w < W; ++w) g[j][w] = uniform_u64(qb.queries[(uint64_t)qq * W + w]);
-                tau[j] = __builtin_amdgcn_readfirstlane(load_relaxed(qb.tau + qq));
-                bias[j] = ok ? 0x7FFFFFFFu - tau[j] : 0x80000000u;
+                for (int w = 0; w < W; ++w) g[j][w] = qp[j * W + w];
+                bias[j] = q0 + j < qb.nq ? 0x7FFFFFFFu - __builtin_amdgcn_readlane(tv, j) : 0x80000000u;
             }
             uint32_t mn = 0xFFFFFFFFu;
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
                 for (int j = 0; j < QB; ++j) {
-                    uint32_t t = bias[j];
+                    const uint64_t x0 = c[r][0] ^ g[j][0];
+                    uint32_t t = bcnt_acc_s((uint32_t)x0, bias[j]);
+                    t = bcnt_acc_v((uint32_t)(x0 >> 32), t);
 #pragma unroll
-                    for (int w = 0; w < W; ++w) t += popc64(c[r][w] ^ g[j][w]);
+                    for (int w = 1; w < W; ++w) {
+                        const uint64_t x = c[r][w] ^ g[j][w];
+                        t = bcnt_acc_v((uint32_t)x, t);
+                        t = bcnt_acc_v((uint32_t)(x >> 32), t);
+                    }
                     mn = mn < t ? mn : t;
                 }
-            if (!__ballot(mn < 0x80000000u)) continue;
-            // slow path: some pair of this wave is within its query's bound
+            if (__ballot(mn < 0x80000000u)) {
+                // slow path: some pair of this wave is within its query's bound
 #pragma unroll 1
-            for (int j = 0; j < QB; ++j) {
-                const uint32_t q = q0 + j;
-                if (q >= qb.nq) break;
-                bool any = false;
+                for (int j = 0; j < QB; ++j) {
+                    const uint32_t q = q0 + j;
+                    if (q >= qb.nq) break;
+                    const uint32_t tau_j = 0x7FFFFFFFu - bias[j];
+                    bool any = false;
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    uint32_t d = hamming<W>(c[r], g[j]);
-                    bool keep = valid[r] && d <= tau[j];
-                    append_candidates(qb, q, keep, d,
-                                      (uint32_t)(base + (uint64_t)r * MIH_BLOCK + tid));
-                    any |= keep;
+                    for (int r = 0; r < R; ++r) {
+                        uint32_t d = hamming<W>(c[r], g[j]);
+                        bool keep = valid[r] && d <= tau_j;
+                        append_candidates(qb, q, keep, d,
+                                          (uint32_t)(base + (uint64_t)r * MIH_BLOCK + tid));
+                        any |= keep;
+                    }
+                    if (__ballot(any)) tighten_tau(qb, q, tau_j);
                 }
-                if (__ballot(any)) tau[j] = tighten_tau(qb, q, tau[j]);
             }
+            tv = tv_next;
+            b = bn;
         }
     }
 }
@@ -164,7 +196,8 @@ hipError_t launch_scan(const mih::LinscanArgs &a, uint32_t num_cus, hipStream_t 
     grid = (a.n + range - 1) / range;
     if (grid < 1) grid = 1;
     const uint32_t nbatches = (a.qb.nq + QB - 1) / QB;
-    linscan_kernel<W, QB, R><<<(uint32_t)grid, MIH_BLOCK, 0, s>>>(a.codes, a.n, a.qb, range, nbatches);
+    linscan_kernel<W, QB, R><<<(uint32_t)grid, MIH_BLOCK, 0, s>>>(a.codes, a.queries_padded, a.n,
+                                                                  a.qb, range, nbatches);
     return hipGetLastError();
 }
 

@@ -231,9 +231,12 @@ hipError_t gather_codes(const uint64_t *codes, const uint32_t *ids, uint64_t n, 
 struct LinscanArgs {
     const uint64_t *codes;
     uint64_t n;
-    QueryBatch qb;
+    QueryBatch qb;               // qb.tau holds linscan_pad(nq) entries
+    const uint64_t *queries_padded;   // [linscan_pad(nq)][W], zero tail
     uint32_t W;
 };
+// Rows of the padded query and bound arrays that the scan reads.
+inline uint32_t linscan_pad(uint32_t nq) { return (nq + 15) / 16 * 16; }
 hipError_t linscan_init(const LinscanArgs &a, uint64_t sample, const uint32_t *tau0,
                         hipStream_t s);
 hipError_t linscan_run(const LinscanArgs &a, uint32_t num_cus, hipStream_t s);

@@ -30,7 +30,8 @@ struct MihArgs {
     uint32_t t_all;           // after this step every code has been found
     uint32_t sorted;          // SORTED tables
     uint32_t inline_codes;    // INLINE codes
-    uint32_t chunk;           // masks per work item (multiple of 512)
+    uint32_t chunk;           // masks per work item (multiple of 64 J)
+    uint32_t J;               // masks per lane per iteration: 4, 8 or 16
     QueryBatch qb;
     uint32_t *t;              // [nq] current step of each query
     const uint32_t *active;   // [n_active] query of each slot, grouped by step
@@ -41,7 +42,8 @@ struct MihArgs {
 };
 
 hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s);
-int mih_round_occupancy(uint32_t W, bool sorted, bool inline_codes);
+int mih_round_occupancy(uint32_t W, bool sorted, bool inline_codes, uint32_t J);
+bool mih_probes_per_lane_ok(uint32_t J);
 // Termination tests and regrouping after a round.  nq bounds the number of
 // active slots.  A.ctrl and ctrl_out may be the same; new_active must differ
 // from A.active.

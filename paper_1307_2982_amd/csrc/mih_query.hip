@@ -30,9 +30,9 @@
 
 namespace {
 
-constexpr int kJ = 8;                       // masks per lane per iteration
+// J: masks per lane per iteration (a tuning knob; 64 J buckets are staged
+// per wave and iteration).
 constexpr uint32_t kWaves = MIH_BLOCK / MIH_WAVE;
-constexpr uint32_t kStage = MIH_WAVE * kJ;  // buckets staged per wave
 
 __device__ __forceinline__ uint32_t binom_calc(uint32_t n, uint32_t r)
 {
@@ -80,7 +80,7 @@ struct WaveStats {
 };
 
 // One step of query q, masks of rank [rb, re) of shell (t mod m, t / m).
-template <int W, bool SORTED, bool INLINE>
+template <int W, bool SORTED, bool INLINE, int J>
 __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t rb, uint32_t re,
                              const uint32_t (*binom)[MIH_BINOM_N], uint32_t *stage_pos,
                              uint32_t *stage_cum, WaveStats &ws)
@@ -96,13 +96,13 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
     const uint32_t key_q = substring<W>(g, T.start, s);
     uint32_t tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
 
-    for (uint32_t base = rb; base < re; base += kStage) {
-        const uint32_t r0 = base + lane * kJ;
-        const uint32_t nmy = r0 < re ? (re - r0 < (uint32_t)kJ ? re - r0 : (uint32_t)kJ) : 0u;
-        uint32_t lo[kJ], cnt[kJ];
+    for (uint32_t base = rb; base < re; base += MIH_WAVE * J) {
+        const uint32_t r0 = base + lane * J;
+        const uint32_t nmy = r0 < re ? (re - r0 < (uint32_t)J ? re - r0 : (uint32_t)J) : 0u;
+        uint32_t lo[J], cnt[J];
         uint32_t mask = nmy ? unrank_mask(r0, rp, s, binom) : 0u;
 #pragma unroll
-        for (int j = 0; j < kJ; ++j) {
+        for (int j = 0; j < J; ++j) {
             cnt[j] = 0;
             lo[j] = 0;
             if ((uint32_t)j < nmy) {
@@ -137,14 +137,14 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
         // candidates before each, then walk the candidates 64 at a time
         uint32_t ne = 0, tc = 0;
 #pragma unroll
-        for (int j = 0; j < kJ; ++j) { ne += cnt[j] ? 1u : 0u; tc += cnt[j]; }
+        for (int j = 0; j < J; ++j) { ne += cnt[j] ? 1u : 0u; tc += cnt[j]; }
         const uint32_t ne_incl = wave_inclusive_sum(ne);
         const uint32_t tc_incl = wave_inclusive_sum(tc);
         const uint32_t NE = __shfl(ne_incl, MIH_WAVE - 1, MIH_WAVE);
         const uint32_t TC = __shfl(tc_incl, MIH_WAVE - 1, MIH_WAVE);
         uint32_t p = ne_incl - ne, c = tc_incl - tc;
 #pragma unroll
-        for (int j = 0; j < kJ; ++j) {
+        for (int j = 0; j < J; ++j) {
             if (cnt[j]) {
                 stage_pos[p] = lo[j];
                 stage_cum[p] = c;
@@ -200,12 +200,12 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
     }
 }
 
-template <int W, bool SORTED, bool INLINE>
+template <int W, bool SORTED, bool INLINE, int J>
 __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
 {
     __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
-    __shared__ uint32_t stage_pos[kWaves][kStage];
-    __shared__ uint32_t stage_cum[kWaves][kStage];
+    __shared__ uint32_t stage_pos[kWaves][MIH_WAVE * J];
+    __shared__ uint32_t stage_cum[kWaves][MIH_WAVE * J];
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += MIH_BLOCK)
         binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
         const uint32_t M = binom_calc(A.tables[t - rp * A.m].len, rp);
         const uint32_t rb = part * chunk;
         const uint32_t re = rb + chunk < M ? rb + chunk : M;
-        process_step<W, SORTED, INLINE>(A, q, t, rb, re, binom, stage_pos[wave], stage_cum[wave], ws);
+        process_step<W, SORTED, INLINE, J>(A, q, t, rb, re, binom, stage_pos[wave], stage_cum[wave], ws);
         if (G.ipq != 1) continue;
         // the whole step belonged to this wave: keep going while steps are small
         for (;;) {
@@ -246,8 +246,8 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
             const uint32_t rpn = tn / A.m;
             const uint32_t Mn = binom_calc(A.tables[tn - rpn * A.m].len, rpn);
             if (Mn > chunk) break;
-            if (Mn) process_step<W, SORTED, INLINE>(A, q, tn, 0, Mn, binom, stage_pos[wave],
-                                                    stage_cum[wave], ws);
+            if (Mn) process_step<W, SORTED, INLINE, J>(A, q, tn, 0, Mn, binom, stage_pos[wave],
+                                                       stage_cum[wave], ws);
             t = tn;
             if (lane == 0) A.t[q] = t;
         }
@@ -342,65 +342,59 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A, const
     }
 }
 
+// Kernel for (W, table mode, codes mode, J); J must be 4, 8 or 16.
 template <int W, bool SORTED, bool INLINE>
-hipError_t launch_round_t(const mih::MihArgs &A, uint32_t grid, hipStream_t s)
+const void *round_kernel_ptr(uint32_t J)
 {
-    mih_round_kernel<W, SORTED, INLINE><<<grid, MIH_BLOCK, 0, s>>>(A);
-    return hipGetLastError();
+    switch (J) {
+    case 4: return reinterpret_cast<const void *>(&mih_round_kernel<W, SORTED, INLINE, 4>);
+    case 8: return reinterpret_cast<const void *>(&mih_round_kernel<W, SORTED, INLINE, 8>);
+    case 16: return reinterpret_cast<const void *>(&mih_round_kernel<W, SORTED, INLINE, 16>);
+    default: return nullptr;
+    }
 }
 
 template <int W>
-hipError_t launch_round_w(const mih::MihArgs &A, uint32_t grid, hipStream_t s)
+const void *round_kernel_w(bool sorted, bool inline_codes, uint32_t J)
 {
-    if (A.sorted) {
-        if (A.inline_codes) return launch_round_t<W, true, true>(A, grid, s);
-        return launch_round_t<W, true, false>(A, grid, s);
-    }
-    if (A.inline_codes) return launch_round_t<W, false, true>(A, grid, s);
-    return launch_round_t<W, false, false>(A, grid, s);
+    if (sorted) return inline_codes ? round_kernel_ptr<W, true, true>(J) : round_kernel_ptr<W, true, false>(J);
+    return inline_codes ? round_kernel_ptr<W, false, true>(J) : round_kernel_ptr<W, false, false>(J);
 }
 
-template <int W, bool SORTED, bool INLINE>
-int occupancy_t()
+const void *round_kernel(uint32_t W, bool sorted, bool inline_codes, uint32_t J)
 {
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, mih_round_kernel<W, SORTED, INLINE>,
-                                                     MIH_BLOCK, 0) != hipSuccess)
-        return 1;
-    return blocks > 0 ? blocks : 1;
+    switch (W) {
+    case 1: return round_kernel_w<1>(sorted, inline_codes, J);
+    case 2: return round_kernel_w<2>(sorted, inline_codes, J);
+    case 3: return round_kernel_w<3>(sorted, inline_codes, J);
+    case 4: return round_kernel_w<4>(sorted, inline_codes, J);
+    default: return nullptr;
+    }
 }
 
 }  // namespace
 
 namespace mih {
 
+bool mih_probes_per_lane_ok(uint32_t J) { return J == 4 || J == 8 || J == 16; }
+
 hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s)
 {
-    switch (A.W) {
-    case 1: return launch_round_w<1>(A, grid, s);
-    case 2: return launch_round_w<2>(A, grid, s);
-    case 3: return launch_round_w<3>(A, grid, s);
-    case 4: return launch_round_w<4>(A, grid, s);
-    default: return hipErrorInvalidValue;
-    }
+    const void *k = round_kernel(A.W, A.sorted, A.inline_codes, A.J);
+    if (!k) return hipErrorInvalidValue;
+    void *args[] = {const_cast<MihArgs *>(&A)};
+    return hipLaunchKernel(k, dim3(grid), dim3(MIH_BLOCK), args, 0, s);
 }
 
-int mih_round_occupancy(uint32_t W, bool sorted, bool inline_codes)
+int mih_round_occupancy(uint32_t W, bool sorted, bool inline_codes, uint32_t J)
 {
-#define MIH_OCC(w)                                                        \
-    case w:                                                               \
-        if (sorted) return inline_codes ? occupancy_t<w, true, true>()    \
-                                        : occupancy_t<w, true, false>();  \
-        return inline_codes ? occupancy_t<w, false, true>()               \
-                            : occupancy_t<w, false, false>();
-    switch (W) {
-        MIH_OCC(1)
-        MIH_OCC(2)
-        MIH_OCC(3)
-        MIH_OCC(4)
-    default: return 1;
+    const void *k = round_kernel(W, sorted, inline_codes, J);
+    int blocks = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, MIH_BLOCK, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
     }
-#undef MIH_OCC
+    return blocks > 0 ? blocks : 1;
 }
 
 hipError_t mih_advance(const MihArgs &A, uint32_t nq, uint32_t *next_t, uint32_t *new_active,
