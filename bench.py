@@ -51,6 +51,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="wall-time budget of the CPU oracle sample")
     ap.add_argument("--threads", type=int, default=None, help="host threads for generation/oracle")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-warmup", type=int, default=30)
+    ap.add_argument("--serve-loads", default="0.5,0.9",
+                    help="fractions of the closed-loop capacity to replay the stream at")
+    ap.add_argument("--serve-slots", type=int, default=16384)
     ap.add_argument("--sweep", action="store_true",
                     help="also time the search over a grid of launch tunings")
     ap.add_argument("--m-sweep", default="",
@@ -111,6 +117,77 @@ def counter_traffic(kernel_sources, counters_file):
     fetch = np.mean(rec["fetch_kib_per_launch"]) * cal["fetch_factor"]
     write = np.mean(rec["write_kib_per_launch"]) * cal["write_factor"]
     return float((fetch + write) * 1024.0), rec
+
+
+def serve_bench(mih, idx, kind, bits, k_choices, args, log_fn):
+    """Continuous-batching serving loop over the built index.
+
+    Requests (1..4096 queries, log-uniform; one k per request from k_choices)
+    arrive as a Poisson stream.  First a closed-loop run (every request
+    submitted at once) measures the capacity; then each load level replays
+    the stream at that fraction of the capacity and records, per request, the
+    time from its arrival to the completion of its last query.
+    """
+    import torch
+    import datagen
+    nreq = args.serve_requests
+    _, sizes, ks = datagen.request_stream(nreq, 1.0, k_choices)
+    total = int(sizes.sum())
+    pool = datagen.query_codes(kind, total, bits, first_row=1_000_000)
+    dpool = to_device(pool)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    mean_size = float(sizes.mean())
+
+    def run(arrivals):
+        srv = mih.Server(idx, max_queries=args.serve_slots)
+        tickets, lat = {}, {}
+        nxt, t0 = 0, time.perf_counter()
+        while len(lat) < nreq:
+            now = time.perf_counter() - t0
+            while nxt < nreq and arrivals[nxt] <= now:
+                tk = srv.submit(dpool[offs[nxt]:offs[nxt + 1]], int(ks[nxt]))
+                tickets[tk] = nxt
+                nxt += 1
+            if len(tickets) > len(lat):
+                for tk in srv.step():
+                    lat[tickets[tk]] = time.perf_counter() - t0
+            elif nxt < nreq:
+                time.sleep(max(0.0, min(0.001, arrivals[nxt] - now)))
+        end = max(lat.values())
+        st = srv.stats()
+        # results of a few requests in the mix against the same queries alone
+        same = True
+        for r in (0, nreq // 2, nreq - 1):
+            tk = [t for t, i in tickets.items() if i == r][0]
+            mi, md = srv.result(tk)
+            bi, bd = idx.knn(dpool[offs[r]:offs[r + 1]], int(ks[r]))
+            same &= bool(torch.equal(mi, bi) and torch.equal(md, bd))
+        srv.close()
+        lat_ms = np.array([(lat[i] - arrivals[i]) * 1e3 for i in range(nreq)])
+        return lat_ms, end, st, same
+
+    lat, end, st, same = run(np.zeros(nreq))
+    closed_qps = total / end
+    log_fn(f"serving closed loop: {nreq} requests, {total} queries in {end:.2f}s -> "
+           f"{closed_qps:,.0f} queries/s; rounds {st['rounds']}; mix == alone: {same}")
+    out = {"requests": nreq, "queries": total, "mean_request_size": round(mean_size, 1),
+           "k_choices": list(k_choices), "slots": args.serve_slots,
+           "closed_loop_qps": round(closed_qps, 1), "closed_loop_same_as_alone": same, "loads": []}
+    warm = min(args.serve_warmup, nreq // 4)
+    for load in [float(x) for x in args.serve_loads.split(",") if x]:
+        rate = load * closed_qps / mean_size
+        arrivals, _, _ = datagen.request_stream(nreq, rate, k_choices)
+        arrivals = arrivals - arrivals[0]
+        lat, end, st, same = run(arrivals)
+        body = lat[warm:]
+        qps = total / end
+        rec = {"load": load, "rate_req_per_s": round(rate, 2), "p50_ms": round(pct(body, 50), 2),
+               "p99_ms": round(pct(body, 99), 2), "mean_ms": round(float(body.mean()), 2),
+               "qps": round(qps, 1), "rounds": st["rounds"], "same_as_alone": same}
+        out["loads"].append(rec)
+        log_fn(f"serving at {load:.0%} load ({rate:.1f} req/s): p50 {rec['p50_ms']} ms, "
+               f"p99 {rec['p99_ms']} ms, {qps:,.0f} queries/s, mix == alone: {same}")
+    return out
 
 
 def pct(a, q):
@@ -263,6 +340,12 @@ def main():
             del ix2
             torch.cuda.synchronize()
 
+    # ---------------- serving loop (continuous batching)
+    serving = None
+    if not args.no_serve:
+        serve_k = datagen.CONFIGS[args.config]["ks"] if args.config != 4 else (1, 10, 100, 1000)
+        serving = serve_bench(mih, idx, kind, bits, serve_k, args, log)
+
     # ---------------- linear scan
     lin = None
     if not args.no_linscan:
@@ -347,7 +430,13 @@ def main():
             "table_mode": info["table_mode"], "codes_mode": info["codes_mode"],
             "index_GiB": round(info["device_bytes"] / 2**30, 2), "build_ms": round(info["build_ms"], 1),
         },
+        "p50_ms": serving["loads"][0]["p50_ms"] if serving and serving["loads"] else None,
+        "p99_ms": serving["loads"][0]["p99_ms"] if serving and serving["loads"] else None,
+        "latency_note": ("per request (arrival to last result), serving loop at "
+                         f"{serving['loads'][0]['load']:.0%} of closed-loop capacity" if serving and serving["loads"]
+                         else None),
         "roofline": roofline,
+        "serving": serving,
         "linscan": lin,
         "cpu_baseline": cpu,
         "parity": {"mih_vs_oracle_sample": parity_oracle,

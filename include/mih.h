@@ -205,6 +205,68 @@ mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
  * range.  Not thread-safe with concurrent mih_knn calls on the same index. */
 mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning);
 
+/* ---- Serving: continuous batching over a built index ------------------
+ *
+ * A server keeps per-query search state for up to max_queries queries
+ * resident on the device and a pool of candidate-buffer memory.  Requests
+ * (each a set of queries with their k) are queued by mih_server_submit and
+ * admitted first in, first out, query by query, whenever a slot and buffer
+ * memory are free; every mih_server_step runs one device round that advances
+ * every admitted query by one search step, so requests submitted while
+ * others are in flight share the device with them.  The result of each query
+ * is the same as mih_knn's, whatever else is in flight.  A server is not
+ * thread-safe; one index may serve several servers and mih_knn calls. */
+typedef struct mih_server mih_server;
+
+typedef struct mih_server_opts {
+    uint32_t max_queries;      /* query slots resident on the device, >= 1      */
+    uint32_t use_graph;        /* 1: replay each round as a captured hipGraph    */
+    uint64_t buffer_entries;   /* candidate-buffer pool in 8-byte entries;
+                                  0 = 8192 per slot.  A query with k needs
+                                  max(2048, 8 k) entries while in flight.        */
+} mih_server_opts;
+
+typedef struct mih_server_stats {
+    uint64_t probes, candidates;   /* summed over all rounds so far             */
+    uint64_t completed_requests;
+    uint32_t rounds;
+    uint32_t in_flight;            /* admitted queries not yet finished          */
+    uint32_t pending_queries;      /* submitted queries waiting for admission    */
+    uint32_t reruns;
+    double search_kernel_ms;
+} mih_server_stats;
+
+/* Create a server on `stream` (a hipStream_t, used by every later call).
+ * The index must outlive the server.  opts NULL: 4096 slots, graphs on. */
+mih_status mih_server_create(const mih_index *idx, const mih_server_opts *opts, void *stream,
+                             mih_server **out);
+
+/* Queue a request.  device queries [nq][bits/64] must stay valid and
+ * unchanged until the request completes; results go to device out_ids /
+ * out_dists in the layout of mih_knn (row i at k_0 + ... + k_{i-1}).
+ * host_k_per_query: per-query k in host memory, or NULL for k.  Each
+ * k <= MIH_K_MAX.  Returns MIH_ERR_CAPACITY (nothing queued) when a query's
+ * buffer could never fit the pool.  Does not wait for the device. */
+mih_status mih_server_submit(mih_server *srv, const uint64_t *queries, uint32_t nq, uint32_t k,
+                             const uint32_t *host_k_per_query, uint32_t *out_ids,
+                             uint32_t *out_dists, uint64_t *ticket);
+
+/* Admit what fits, run one round, finalize finished queries.  Writes up to
+ * max_completed tickets of requests completed since the last call to
+ * host `completed` and their number to *n_completed (more stay queued for
+ * the next call).  Blocking: outputs of reported requests are on the device
+ * when it returns. */
+mih_status mih_server_step(mih_server *srv, uint64_t *completed, uint32_t max_completed,
+                           uint32_t *n_completed);
+
+/* *done = 1 when the request has completed (its outputs are written). */
+mih_status mih_server_poll(const mih_server *srv, uint64_t ticket, int *done);
+
+mih_status mih_server_get_stats(mih_server *srv, mih_server_stats *stats);
+
+/* Release a server (pending and in-flight requests are dropped). */
+void mih_server_destroy(mih_server *srv);
+
 /* Fill *info (host memory) with the index's shape and modes. */
 mih_status mih_index_get_info(const mih_index *idx, mih_index_info *info);
 

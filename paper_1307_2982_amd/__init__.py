@@ -84,7 +84,8 @@ class Tuning(ctypes.Structure):
 
 EXPORTED = ["mih_build", "mih_knn", "mih_knn_ex", "linscan_knn", "linscan_knn_ex", "mih_free",
             "mih_status_str", "mih_index_get_info", "mih_index_table", "mih_get_tuning",
-            "mih_set_tuning"]
+            "mih_set_tuning", "mih_server_create", "mih_server_submit", "mih_server_step",
+            "mih_server_poll", "mih_server_get_stats", "mih_server_destroy"]
 
 _lib = None
 
@@ -125,6 +126,18 @@ def load():
     L.mih_get_tuning.restype = i32
     L.mih_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.mih_set_tuning.restype = i32
+    L.mih_server_create.argtypes = [vp, ctypes.POINTER(ServerOpts), vp, ctypes.POINTER(vp)]
+    L.mih_server_create.restype = i32
+    L.mih_server_submit.argtypes = [vp, vp, u32, u32, vp, vp, vp, ctypes.POINTER(u64)]
+    L.mih_server_submit.restype = i32
+    L.mih_server_step.argtypes = [vp, vp, u32, ctypes.POINTER(u32)]
+    L.mih_server_step.restype = i32
+    L.mih_server_poll.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_int)]
+    L.mih_server_poll.restype = i32
+    L.mih_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.mih_server_get_stats.restype = i32
+    L.mih_server_destroy.argtypes = [vp]
+    L.mih_server_destroy.restype = None
     _lib = L
     return L
 
@@ -276,6 +289,100 @@ def linscan_knn(codes: torch.Tensor, queries: torch.Tensor, k, stats: bool = Fal
     _check(rc, "linscan_knn")
     ids, dists = _shape(ids, dists, total, nq, kk, kl)
     return (ids, dists, st.as_dict()) if stats else (ids, dists)
+
+
+# ------------------------------------------------------------------ serving
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_queries", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
+                ("buffer_entries", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("probes", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
+                ("completed_requests", ctypes.c_uint64), ("rounds", ctypes.c_uint32),
+                ("in_flight", ctypes.c_uint32), ("pending_queries", ctypes.c_uint32),
+                ("reruns", ctypes.c_uint32), ("search_kernel_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Server:
+    """Continuous-batching server over an index (mih_server_* in the C ABI).
+
+    submit() queues a request and returns its ticket; step() admits what fits,
+    runs one device round and returns the tickets completed in it.  Each
+    request's (ids, dists) tensors are available from result(ticket) once
+    completed.
+    """
+
+    def __init__(self, index: Index, max_queries: int = 4096, buffer_entries: int = 0,
+                 use_graph: bool = True):
+        L = load()
+        self.index = index
+        self._h = ctypes.c_void_p()
+        opts = ServerOpts(max_queries, 1 if use_graph else 0, buffer_entries)
+        _check(L.mih_server_create(index._h, ctypes.byref(opts), _stream(), ctypes.byref(self._h)),
+               "mih_server_create")
+        self._live = {}      # ticket -> (queries, ids, dists, shape)
+        self._done = {}
+
+    def close(self):
+        if self._h:
+            load().mih_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, queries: torch.Tensor, k) -> int:
+        queries = _codes_arg(queries, "queries")
+        nq = queries.shape[0]
+        if isinstance(k, int):
+            kk, karr, kl = k, None, None
+        else:
+            kl = [int(x) for x in k]
+            kk, karr = 0, (ctypes.c_uint32 * nq)(*kl)
+        ids, dists, total = _outputs(nq, kk, kl, queries.device)
+        t = ctypes.c_uint64()
+        _check(load().mih_server_submit(self._h, queries.data_ptr(), nq, kk, karr, ids.data_ptr(),
+                                        dists.data_ptr(), ctypes.byref(t)), "mih_server_submit")
+        self._live[t.value] = (queries, ids, dists, (total, nq, kk, kl))
+        return t.value
+
+    def step(self, max_completed: int = 4096):
+        buf = (ctypes.c_uint64 * max_completed)()
+        n = ctypes.c_uint32()
+        _check(load().mih_server_step(self._h, buf, max_completed, ctypes.byref(n)), "mih_server_step")
+        out = [buf[i] for i in range(n.value)]
+        for t in out:
+            q, ids, dists, shape = self._live.pop(t)
+            self._done[t] = _shape(ids, dists, *shape)
+        return out
+
+    def result(self, ticket: int):
+        return self._done.pop(ticket)
+
+    def done(self, ticket: int) -> bool:
+        d = ctypes.c_int()
+        _check(load().mih_server_poll(self._h, ticket, ctypes.byref(d)), "mih_server_poll")
+        return bool(d.value)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().mih_server_get_stats(self._h, ctypes.byref(st)), "mih_server_get_stats")
+        return st.as_dict()
+
+    def drain(self):
+        """Step until every submitted request has completed."""
+        done = []
+        while self._live:
+            done += self.step()
+        return done
 
 
 # ------------------------------------------------------------------ plumbing

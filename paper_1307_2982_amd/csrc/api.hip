@@ -9,8 +9,7 @@
 #include <mutex>
 #include <vector>
 
-#include "mih_common.h"
-#include "mih_query.h"
+#include "engine.h"
 
 namespace {
 
@@ -235,40 +234,20 @@ uint32_t scan_cap(uint32_t k) { return k == 0 ? 0u : std::max<uint32_t>(4096u, 1
 
 // ============================================================== the index
 
-struct mih_index {
-    int device = 0;
-    const uint64_t *codes = nullptr;
-    uint64_t n = 0;
-    uint32_t bits = 0, W = 0, m = 0;
-    uint32_t table_mode = 0, codes_mode = 0;
-    uint32_t len[MIH_M_MAX] = {}, start[MIH_M_MAX] = {}, dir_bits[MIH_M_MAX] = {};
-    uint32_t t_all = 0;
-    TableDev tables_host[MIH_M_MAX] = {};
-    TableDev *tables_dev = nullptr;
-    std::vector<void *> allocs;
-    uint64_t device_bytes = 0;
-    double build_ms = 0;
-    mih_tuning tuning = {4, 8192, 0};
-    std::mutex mu;
-    Scratch scratch, rerun_scratch;
-    mih::Control *ctrl_host = nullptr;   // pinned
+hipError_t mih_index::alloc(void **p, uint64_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes ? bytes : 4);
+    if (e != hipSuccess) { (void)hipGetLastError(); *p = nullptr; return e; }
+    allocs.push_back(*p);
+    device_bytes += bytes;
+    return hipSuccess;
+}
 
-    hipError_t alloc(void **p, uint64_t bytes)
-    {
-        hipError_t e = hipMalloc(p, bytes ? bytes : 4);
-        if (e != hipSuccess) { (void)hipGetLastError(); *p = nullptr; return e; }
-        allocs.push_back(*p);
-        device_bytes += bytes;
-        return hipSuccess;
-    }
-    ~mih_index()
-    {
-        for (void *p : allocs) (void)hipFree(p);
-        scratch.release();
-        rerun_scratch.release();
-        if (ctrl_host) (void)hipHostFree(ctrl_host);
-    }
-};
+mih_index::~mih_index()
+{
+    batch_engine.reset();
+    for (void *p : allocs) (void)hipFree(p);
+}
 
 namespace {
 
@@ -400,162 +379,25 @@ mih_status linscan_batch(const uint64_t *codes, uint64_t n, uint32_t bits, Batch
 
 // ---------------------------------------------------------------- MIH
 
-mih_status mih_batch(mih_index *ix, BatchSpec &b, uint32_t *out_ids, uint32_t *out_dists,
-                     hipStream_t s, Scratch &mem, int depth, mih_query_stats *stats);
-
-mih_status rerun_mih(mih_index *ix, const BatchSpec &b, BatchBufs &B, uint32_t *out_ids,
-                     uint32_t *out_dists, hipStream_t s, int depth, mih_query_stats *stats)
+bool use_graphs()
 {
-    uint32_t novf = 0;
-    MIH_TRY(download(&novf, B.ovf_count, sizeof(uint32_t), s));
-    if (novf == 0) return MIH_OK;
-    if (depth > 2) return MIH_ERR_DEVICE;
-    if (stats) stats->reruns += novf;
-    const uint32_t W = ix->W;
-    std::vector<uint32_t> list(novf);
-    MIH_TRY(download(list.data(), B.ovf_list, sizeof(uint32_t) * novf, s));
-    Carver c0;
-    c0.take<uint32_t>(novf); c0.take<uint32_t>(novf); c0.take<uint32_t>(novf);
-    c0.take<uint64_t>((uint64_t)novf * W);
-    Scratch tmp;
-    MIH_TRY(tmp.ensure(c0.used));
-    Carver c;
-    c.base = (char *)tmp.ptr;
-    uint32_t *dlist = c.take<uint32_t>(novf);
-    uint32_t *dtau = c.take<uint32_t>(novf);
-    uint32_t *dcap = c.take<uint32_t>(novf);
-    uint64_t *dq = c.take<uint64_t>((uint64_t)novf * W);
-    mih_status st = MIH_OK;
-    do {
-        if (upload(dlist, list.data(), sizeof(uint32_t) * novf, s) != hipSuccess) { st = MIH_ERR_DEVICE; break; }
-        if (mih::exact_bounds(B.qb, dlist, novf, dtau, dcap, s) != hipSuccess ||
-            mih::gather_rows(b.queries, dlist, novf, W, dq, s) != hipSuccess) { st = MIH_ERR_DEVICE; break; }
-        BatchSpec rb;
-        rb.queries = dq;
-        rb.nq = novf;
-        rb.tau0 = dtau;
-        rb.cap.resize(novf);
-        if (download(rb.cap.data(), dcap, sizeof(uint32_t) * novf, s) != hipSuccess) { st = MIH_ERR_DEVICE; break; }
-        rb.k.resize(novf);
-        rb.row_off.resize(novf);
-        for (uint32_t i = 0; i < novf; ++i) {
-            rb.k[i] = b.k[list[i]];
-            rb.row_off[i] = b.row_off[list[i]];
-            if (rb.cap[i] == 0 && rb.k[i]) rb.cap[i] = 1;
-        }
-        st = mih_batch(ix, rb, out_ids, out_dists, s, ix->rerun_scratch, depth + 1, stats);
-    } while (0);
-    (void)hipStreamSynchronize(s);
-    tmp.release();
-    return st;
+    static const bool off = std::getenv("MIH_NO_GRAPH") != nullptr;
+    return !off;
 }
 
-mih_status mih_batch(mih_index *ix, BatchSpec &b, uint32_t *out_ids, uint32_t *out_dists,
-                     hipStream_t s, Scratch &mem, int depth, mih_query_stats *stats)
+// Runs one request of nq queries through an engine until it completes.
+mih_status engine_batch(mih::Engine &eng, const uint64_t *queries, uint32_t nq,
+                        const std::vector<uint32_t> &k, const std::vector<uint64_t> &row_off,
+                        uint32_t *out_ids, uint32_t *out_dists)
 {
-    if (b.nq == 0) return MIH_OK;
-    const uint32_t W = ix->W, bits = ix->bits;
-    std::vector<uint64_t> buf_off;
-    const uint64_t words = buffer_words(b, buf_off);
-    BatchBufs B;
-    Carver c0;
-    carve_batch(c0, b, bits, W, words, ix->t_all + 1, B);
-    MIH_TRY(mem.ensure(c0.used));
-    Carver c;
-    c.base = (char *)mem.ptr;
-    carve_batch(c, b, bits, W, words, ix->t_all + 1, B);
-
-    std::vector<uint32_t> active;
-    active.reserve(b.nq);
-    for (uint32_t i = 0; i < b.nq; ++i)
-        if (b.k[i]) active.push_back(i);
-    mih::Group g0 = {0, (uint32_t)active.size(), 1, 0, 0};
-    mih::Control c_init = {(uint32_t)active.size(), 1, (uint64_t)active.size()};
-
-    MIH_TRY(upload((void *)B.qb.k, b.k.data(), sizeof(uint32_t) * b.nq, s));
-    MIH_TRY(upload((void *)B.qb.cap, b.cap.data(), sizeof(uint32_t) * b.nq, s));
-    MIH_TRY(upload((void *)B.qb.buf_off, buf_off.data(), sizeof(uint64_t) * b.nq, s));
-    MIH_TRY(upload(B.row_off, b.row_off.data(), sizeof(uint64_t) * b.nq, s));
-    MIH_TRY(upload(B.active0, active.data(), sizeof(uint32_t) * active.size(), s));
-    MIH_TRY(upload(B.groups, &g0, sizeof(g0), s));
-    MIH_TRY(upload(B.ctrl, &c_init, sizeof(c_init), s));
-    MIH_TRY(mih::fill_u32(B.qb.count, b.nq, 0u, s));
-    MIH_TRY(mih::fill_u32(B.qb.hist, (uint64_t)b.nq * (bits + 1), 0u, s));
-    MIH_TRY(mih::fill_u32(B.t, b.nq, 0u, s));
-    MIH_TRY(mih::fill_u64((uint64_t *)B.work, 1, 0ull, s));
-    MIH_TRY(mih::fill_u64((uint64_t *)B.stats, 4, 0ull, s));
-    if (b.tau0)
-        MIH_TRY(hipMemcpyAsync(B.qb.tau, b.tau0, sizeof(uint32_t) * b.nq, hipMemcpyDeviceToDevice, s));
-    else
-        MIH_TRY(mih::fill_u32(B.qb.tau, b.nq, bits, s));
-
-    mih::MihArgs A;
-    A.tables = ix->tables_dev;
-    A.codes = ix->codes;
-    A.n = ix->n;
-    A.W = W;
-    A.m = ix->m;
-    A.bits = bits;
-    A.t_all = ix->t_all;
-    A.sorted = ix->table_mode == MIH_TABLE_SORTED;
-    A.inline_codes = ix->codes_mode == MIH_CODES_INLINE;
-    A.chunk = ix->tuning.chunk;
-    A.J = ix->tuning.probes_per_lane;
-    A.qb = B.qb;
-    A.t = B.t;
-    A.groups = B.groups;
-    A.ctrl = B.ctrl;
-    A.work = B.work;
-    A.stats = B.stats;
-    uint32_t per_cu = (uint32_t)mih::mih_round_occupancy(W, A.sorted, A.inline_codes, A.J);
-    if (ix->tuning.blocks_per_cu && ix->tuning.blocks_per_cu < per_cu) per_cu = ix->tuning.blocks_per_cu;
-    const uint32_t grid = num_cus() * per_cu;
-
-    uint32_t n_active = (uint32_t)active.size();
-    uint32_t *cur = B.active0, *nxt = B.active1;
-    uint32_t rounds = 0;
-    EventPair ev_round(stats != nullptr);
-    while (n_active > 0) {
-        if (rounds > 4 * ix->t_all + 16) return MIH_ERR_DEVICE;   // cannot happen: t grows each round
-        A.active = cur;
-        ev_round.begin(s);
-        MIH_TRY(mih::mih_round(A, grid, s));
-        ev_round.end(s);
-        MIH_TRY(mih::mih_advance(A, b.nq, B.next_t, nxt, B.groups, B.ctrl, s));
-        MIH_TRY(hipMemcpyAsync(ix->ctrl_host, B.ctrl, sizeof(mih::Control), hipMemcpyDeviceToHost, s));
-        MIH_TRY(hipStreamSynchronize(s));
-        n_active = ix->ctrl_host->n_active;
-        std::swap(cur, nxt);
-        ++rounds;
-        if (stats) {
-            stats->search_kernel_ms += ev_round.ms();
-            stats->search_launches += 1;
-        }
+    std::vector<uint64_t> completed;
+    eng.submit(queries, nq, k.data(), row_off.data(), out_ids, out_dists);
+    uint64_t guard = 0;
+    while (!eng.idle()) {
+        MIH_TRY(eng.step(completed));
+        if (++guard > (1ull << 24)) return MIH_ERR_DEVICE;   // cannot happen: every round advances
     }
-
-    mih::FinalArgs F;
-    F.qb = B.qb;
-    F.row_off = B.row_off;
-    F.out_ids = out_ids;
-    F.out_dists = out_dists;
-    F.overflow_list = B.ovf_list;
-    F.overflow_count = B.ovf_count;
-    MIH_TRY(mih::find_overflow(F, s));
-    MIH_TRY(mih::finalize_topk(F, s));
-    MIH_TRY(hipStreamSynchronize(s));
-    if (stats) {
-        unsigned long long st4[4] = {0, 0, 0, 0};
-        MIH_TRY(download(st4, B.stats, sizeof(st4), s));
-        std::vector<uint32_t> t(b.nq), cnt(b.nq);
-        MIH_TRY(download(t.data(), B.t, sizeof(uint32_t) * b.nq, s));
-        MIH_TRY(download(cnt.data(), B.qb.count, sizeof(uint32_t) * b.nq, s));
-        stats->probes += st4[0];
-        stats->candidates += st4[1];
-        for (uint32_t i = 0; i < b.nq; ++i)
-            if (b.k[i]) { stats->steps += (uint64_t)t[i] + 1; stats->appended += cnt[i]; }
-        stats->rounds += rounds;
-    }
-    return rerun_mih(ix, b, B, out_ids, out_dists, s, depth, stats);
+    return MIH_OK;
 }
 
 mih_status check_query_args(uint32_t bits, const uint64_t *queries, uint32_t nq,
@@ -693,8 +535,7 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     mih_status st = MIH_OK;
     Scratch tk1, tk2, ti2, tmp;
     do {
-        hipError_t e = hipHostMalloc((void **)&ix->ctrl_host, sizeof(mih::Control), 0);
-        if (e != hipSuccess) { st = from_hip(e); break; }
+        hipError_t e;
         if ((e = tk1.ensure(n * 4 + 4)) != hipSuccess || (e = tk2.ensure(n * 4 + 4)) != hipSuccess ||
             (e = ti2.ensure(n * 4 + 4)) != hipSuccess ||
             (e = tmp.ensure(std::max(mih::radix_tmp_words(n), mih::scan_tmp_words(max_entries)) * 4)) !=
@@ -771,17 +612,43 @@ mih_status mih_knn_ex(const mih_index *cidx, const uint64_t *queries, uint32_t n
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lock(ix->mu);
     if (stats) std::memset(stats, 0, sizeof(*stats));
-    BatchSpec b;
-    b.queries = queries;
-    b.nq = nq;
-    MIH_TRY_STATUS(read_k(nq, k, k_per_query, s, b.k));
-    row_offsets(b.k, b.row_off);
-    b.cap.resize(nq);
-    for (uint32_t i = 0; i < nq; ++i) b.cap[i] = mih_cap(b.k[i]);
-    mih_status st = mih_batch(ix, b, out_ids, out_dists, s, ix->scratch, 0, stats);
-    (void)hipStreamSynchronize(s);
-    if (stats) stats->elapsed_ms = ms_since(t0);
-    return st;
+    std::vector<uint32_t> kv;
+    MIH_TRY_STATUS(read_k(nq, k, k_per_query, s, kv));
+    std::vector<uint64_t> row_off;
+    row_offsets(kv, row_off);
+    uint32_t slots = 0;
+    uint64_t pool = 0;
+    for (uint32_t v : kv)
+        if (v) { slots++; pool += mih::search_capacity(v); }
+    if (slots == 0) return MIH_OK;
+    // one engine per index, kept while it is large enough
+    if (!ix->batch_engine || ix->batch_engine->slots() < slots || ix->batch_engine->pool_entries() < pool) {
+        ix->batch_engine.reset();
+        std::unique_ptr<mih::Engine> e(new (std::nothrow) mih::Engine(ix, s));
+        if (!e) return MIH_ERR_NOMEM;
+        hipError_t he = e->init(slots, pool, use_graphs());
+        if (he != hipSuccess) { (void)hipGetLastError(); return from_hip(he); }
+        ix->batch_engine = std::move(e);
+    }
+    mih::Engine &eng = *ix->batch_engine;
+    eng.set_stream(s);
+    MIH_TRY(eng.reset_stats());
+    mih_status st = engine_batch(eng, queries, nq, kv, row_off, out_ids, out_dists);
+    if (st != MIH_OK) { ix->batch_engine.reset(); return st; }
+    if (stats) {
+        mih::EngineStats es;
+        MIH_TRY(eng.read_stats(es));
+        stats->probes = es.probes;
+        stats->candidates = es.candidates;
+        stats->appended = es.appended;
+        stats->steps = es.steps;
+        stats->rounds = es.rounds;
+        stats->reruns = es.reruns;
+        stats->search_kernel_ms = es.search_kernel_ms;
+        stats->search_launches = es.search_launches;
+        stats->elapsed_ms = ms_since(t0);
+    }
+    return MIH_OK;
 }
 
 mih_status mih_knn(const mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
@@ -828,6 +695,7 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning)
     if (tuning->blocks_per_cu > 64) return MIH_ERR_INVALID;
     std::lock_guard<std::mutex> lock(idx->mu);
     idx->tuning = *tuning;
+    idx->tuning_version++;
     return MIH_OK;
 }
 
@@ -845,5 +713,103 @@ mih_status mih_index_table(const mih_index *idx, uint32_t j, mih_table_view *vie
     view->dir_bits = idx->table_mode == MIH_TABLE_SORTED ? T.dir_bits : 0;
     return MIH_OK;
 }
+
+}  // extern "C"
+
+// ============================================================== serving
+
+struct mih_server {
+    mih_index *ix = nullptr;
+    std::unique_ptr<mih::Engine> eng;
+    std::deque<uint64_t> backlog;   // completed tickets not yet reported
+    uint64_t completed = 0;
+};
+
+extern "C" {
+
+mih_status mih_server_create(const mih_index *cidx, const mih_server_opts *opts, void *stream,
+                             mih_server **out)
+{
+    if (!cidx || !out) return MIH_ERR_INVALID;
+    mih_server_opts o = {4096, 1, 0};
+    if (opts) o = *opts;
+    if (o.max_queries == 0) return MIH_ERR_INVALID;
+    const uint64_t pool = o.buffer_entries ? o.buffer_entries : 8192ull * o.max_queries;
+    mih_server *srv = new (std::nothrow) mih_server();
+    if (!srv) return MIH_ERR_NOMEM;
+    srv->ix = const_cast<mih_index *>(cidx);
+    srv->eng.reset(new (std::nothrow) mih::Engine(srv->ix, (hipStream_t)stream));
+    if (!srv->eng) { delete srv; return MIH_ERR_NOMEM; }
+    hipError_t e = srv->eng->init(o.max_queries, pool, o.use_graph != 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete srv;
+        return from_hip(e);
+    }
+    *out = srv;
+    return MIH_OK;
+}
+
+mih_status mih_server_submit(mih_server *srv, const uint64_t *queries, uint32_t nq, uint32_t k,
+                             const uint32_t *host_k_per_query, uint32_t *out_ids,
+                             uint32_t *out_dists, uint64_t *ticket)
+{
+    if (!srv || !ticket) return MIH_ERR_INVALID;
+    MIH_TRY_STATUS(check_query_args(srv->ix->bits, queries, nq, out_ids, out_dists));
+    std::vector<uint32_t> kv(nq, k);
+    if (host_k_per_query) kv.assign(host_k_per_query, host_k_per_query + nq);
+    for (uint32_t v : kv) {
+        if (v > MIH_K_MAX) return MIH_ERR_UNSUPPORTED;
+        if (!srv->eng->can_ever_fit(v)) return MIH_ERR_CAPACITY;
+    }
+    std::vector<uint64_t> row_off;
+    row_offsets(kv, row_off);
+    *ticket = srv->eng->submit(queries, nq, kv.data(), row_off.data(), out_ids, out_dists);
+    return MIH_OK;
+}
+
+mih_status mih_server_step(mih_server *srv, uint64_t *completed, uint32_t max_completed,
+                           uint32_t *n_completed)
+{
+    if (!srv || !n_completed || (max_completed && !completed)) return MIH_ERR_INVALID;
+    std::vector<uint64_t> done;
+    hipError_t e = srv->eng->step(done);
+    if (e != hipSuccess) { (void)hipGetLastError(); return from_hip(e); }
+    srv->completed += done.size();
+    for (uint64_t t : done) srv->backlog.push_back(t);
+    uint32_t n = 0;
+    while (n < max_completed && !srv->backlog.empty()) {
+        completed[n++] = srv->backlog.front();
+        srv->backlog.pop_front();
+    }
+    *n_completed = n;
+    return MIH_OK;
+}
+
+mih_status mih_server_poll(const mih_server *srv, uint64_t ticket, int *done)
+{
+    if (!srv || !done) return MIH_ERR_INVALID;
+    *done = srv->eng->done(ticket) ? 1 : 0;
+    return MIH_OK;
+}
+
+mih_status mih_server_get_stats(mih_server *srv, mih_server_stats *st)
+{
+    if (!srv || !st) return MIH_ERR_INVALID;
+    mih::EngineStats es;
+    MIH_TRY(srv->eng->read_stats(es));
+    std::memset(st, 0, sizeof(*st));
+    st->probes = es.probes;
+    st->candidates = es.candidates;
+    st->completed_requests = srv->completed;
+    st->rounds = es.rounds;
+    st->in_flight = srv->eng->in_flight();
+    st->pending_queries = srv->eng->pending_queries();
+    st->reruns = es.reruns;
+    st->search_kernel_ms = es.search_kernel_ms;
+    return MIH_OK;
+}
+
+void mih_server_destroy(mih_server *srv) { delete srv; }
 
 }  // extern "C"

@@ -1,0 +1,155 @@
+// Host side of the multi-index search: the index object and the engine that
+// runs queries through the device rounds.
+#pragma once
+
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "mih_common.h"
+#include "mih_query.h"
+
+namespace mih {
+
+// A first-fit allocator of buffer entries inside one device region.
+class PoolAlloc {
+public:
+    void reset(uint64_t size);
+    bool alloc(uint64_t n, uint64_t &off);
+    void release(uint64_t off, uint64_t n);
+    uint64_t size() const { return size_; }
+    uint64_t free_total() const { return free_total_; }
+    uint64_t largest_free() const;
+
+private:
+    std::map<uint64_t, uint64_t> free_;   // offset -> length
+    uint64_t size_ = 0, free_total_ = 0;
+};
+
+// Candidate-buffer capacity given to a query with this k (entries).
+inline uint32_t search_capacity(uint32_t k) { return k == 0 ? 0u : (k * 8u > 2048u ? k * 8u : 2048u); }
+
+class Engine;
+
+}  // namespace mih
+
+struct mih_index {
+    int device = 0;
+    const uint64_t *codes = nullptr;
+    uint64_t n = 0;
+    uint32_t bits = 0, W = 0, m = 0;
+    uint32_t table_mode = 0, codes_mode = 0;
+    uint32_t len[MIH_M_MAX] = {}, start[MIH_M_MAX] = {}, dir_bits[MIH_M_MAX] = {};
+    uint32_t t_all = 0;
+    TableDev tables_host[MIH_M_MAX] = {};
+    TableDev *tables_dev = nullptr;
+    std::vector<void *> allocs;
+    uint64_t device_bytes = 0;
+    double build_ms = 0;
+    mih_tuning tuning = {4, 8192, 0};
+    uint32_t tuning_version = 0;
+    std::mutex mu;
+    std::unique_ptr<mih::Engine> batch_engine;   // reused by mih_knn calls
+
+    hipError_t alloc(void **p, uint64_t bytes);
+    ~mih_index();
+};
+
+namespace mih {
+
+struct EngineStats {
+    uint64_t probes = 0, candidates = 0, steps = 0, appended = 0;
+    uint32_t rounds = 0, reruns = 0;
+    double search_kernel_ms = 0;
+    uint32_t search_launches = 0;
+};
+
+// Runs queries over an index in rounds.  Per-query state lives in `slots`
+// device slots; candidate buffers come from a pool of `pool_entries`
+// entries.  Requests are admitted first in, first out, query by query, as
+// slots and buffer memory become free; every query's result is independent
+// of what else is in flight.
+class Engine {
+public:
+    Engine(mih_index *ix, hipStream_t s) : ix_(ix), s_(s) {}
+    ~Engine();
+    hipError_t init(uint32_t slots, uint64_t pool_entries, bool use_graph);
+    uint32_t slots() const { return S_; }
+    uint64_t pool_entries() const { return pool_.size(); }
+
+    // A request of nq queries with per-query k (host), output rows at
+    // row_off[i] in out_ids / out_dists (device).  Returns its ticket.
+    uint64_t submit(const uint64_t *queries, uint32_t nq, const uint32_t *k,
+                    const uint64_t *row_off, uint32_t *out_ids, uint32_t *out_dists);
+    // One round; tickets of requests completed in it are appended.
+    hipError_t step(std::vector<uint64_t> &completed);
+    bool idle() const { return in_flight_ == 0 && pending_.empty() && reruns_.empty(); }
+    bool done(uint64_t ticket) const { return reqs_.find(ticket) == reqs_.end(); }
+    uint32_t in_flight() const { return in_flight_; }
+    uint32_t pending_queries() const;
+    hipError_t read_stats(EngineStats &out);
+    hipError_t reset_stats();
+    void set_stream(hipStream_t s) { s_ = s; }
+    bool can_ever_fit(uint32_t k) const { return search_capacity(k) <= pool_.size(); }
+
+private:
+    struct Req {
+        const uint64_t *queries;
+        uint32_t nq;
+        std::vector<uint32_t> k;
+        std::vector<uint64_t> row_off;
+        uint32_t *out_ids, *out_dists;
+        uint32_t next = 0, done = 0;
+    };
+    struct SlotInfo {
+        uint64_t ticket = 0;
+        uint32_t query = 0;
+        uint64_t buf_off = 0, buf_len = 0;
+    };
+    struct Rerun {
+        uint32_t slot, tau0, cap;
+    };
+
+    hipError_t admit();
+    hipError_t run_round();
+    hipError_t capture_graph();
+    void fill_args(MihArgs &A) const;
+
+    mih_index *ix_;
+    hipStream_t s_;
+    uint32_t S_ = 0;
+    bool use_graph_ = false;
+    void *dev_ = nullptr;      // slot state, one allocation
+    uint64_t *pool_mem_ = nullptr;
+    PoolAlloc pool_;
+    QueryBatch qb_ = {};
+    uint32_t *t_ = nullptr, *active_ = nullptr, *active_tmp_ = nullptr, *next_t_ = nullptr;
+    uint32_t *new_slots_ = nullptr, *done_list_ = nullptr, *ovf_list_ = nullptr;
+    uint32_t *bound_tau_ = nullptr, *bound_cap_ = nullptr;
+    uint64_t *out_ids_ = nullptr, *out_dists_ = nullptr;
+    Group *groups_ = nullptr;
+    Control *ctrl_ = nullptr;
+    unsigned long long *work_ = nullptr, *stats_ = nullptr;
+    AdmitRec *admit_dev_ = nullptr;
+    Control *ctrl_host_ = nullptr;   // pinned
+    hipEvent_t ev_a_ = nullptr, ev_b_ = nullptr;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t graph_exec_ = nullptr;
+    uint32_t graph_tuning_version_ = ~0u;
+    uint32_t round_grid_ = 0;
+
+    std::vector<uint32_t> free_slots_;
+    std::vector<SlotInfo> slot_info_;
+    std::unordered_map<uint64_t, Req> reqs_;
+    std::deque<uint64_t> pending_;
+    std::deque<Rerun> reruns_;
+    uint64_t next_ticket_ = 1;
+    uint32_t in_flight_ = 0;       // admitted queries not yet finished
+    bool ctrl_has_active_ = false;
+    EngineStats stats_host_;
+};
+
+}  // namespace mih

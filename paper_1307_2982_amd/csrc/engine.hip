@@ -1,0 +1,456 @@
+// The engine that runs multi-index kNN queries in device rounds.
+//
+// A round is three kernels: regroup (surviving and newly admitted queries
+// become the active list, grouped by step), the persistent search kernel (one
+// step of every active query) and advance (termination tests; finished
+// queries are listed).  The three, with the copy of the control block to
+// pinned host memory, are captured once in a hipGraph and replayed every
+// round.  Between rounds the host admits queries into free slots (first in,
+// first out, as long as slots and candidate-buffer memory allow), finalizes
+// the finished ones into their requests' output rows, and re-admits the rare
+// query whose buffer overflowed with its exact bound and an exact capacity.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "engine.h"
+
+namespace mih {
+
+namespace {
+
+uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
+
+uint32_t cu_count()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return (uint32_t)cus;
+}
+
+hipError_t sync_copy(void *dst, const void *src, size_t bytes, hipMemcpyKind kind, hipStream_t s)
+{
+    if (!bytes) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ PoolAlloc
+
+void PoolAlloc::reset(uint64_t size)
+{
+    free_.clear();
+    if (size) free_[0] = size;
+    size_ = size;
+    free_total_ = size;
+}
+
+bool PoolAlloc::alloc(uint64_t n, uint64_t &off)
+{
+    if (n == 0) { off = 0; return true; }
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second >= n) {
+            off = it->first;
+            uint64_t rest = it->second - n;
+            free_.erase(it);
+            if (rest) free_[off + n] = rest;
+            free_total_ -= n;
+            return true;
+        }
+    }
+    return false;
+}
+
+void PoolAlloc::release(uint64_t off, uint64_t n)
+{
+    if (n == 0) return;
+    auto it = free_.emplace(off, n).first;
+    free_total_ += n;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            free_.erase(it);
+        }
+    }
+}
+
+uint64_t PoolAlloc::largest_free() const
+{
+    uint64_t b = 0;
+    for (auto &kv : free_) b = std::max(b, kv.second);
+    return b;
+}
+
+// ------------------------------------------------------------ Engine
+
+Engine::~Engine()
+{
+    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    if (ev_a_) (void)hipEventDestroy(ev_a_);
+    if (ev_b_) (void)hipEventDestroy(ev_b_);
+    if (ctrl_host_) (void)hipHostFree(ctrl_host_);
+    if (pool_mem_) (void)hipFree(pool_mem_);
+    if (dev_) (void)hipFree(dev_);
+}
+
+hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
+{
+    S_ = slots ? slots : 1;
+    use_graph_ = use_graph;
+    const uint32_t W = ix_->W, nb = ix_->bits + 1;
+    uint64_t used = 0;
+    auto take = [&](uint64_t bytes) { uint64_t o = used; used += align256(bytes ? bytes : 1); return o; };
+    const uint64_t o_q = take(8ull * S_ * W), o_k = take(4ull * S_), o_tau = take(4ull * S_ + 64),
+                   o_cnt = take(4ull * S_), o_cap = take(4ull * S_), o_boff = take(8ull * S_),
+                   o_hist = take(4ull * S_ * nb), o_t = take(4ull * S_), o_oi = take(8ull * S_),
+                   o_od = take(8ull * S_), o_act = take(4ull * S_), o_tmp = take(4ull * S_),
+                   o_nt = take(4ull * S_), o_new = take(4ull * S_), o_done = take(4ull * S_),
+                   o_ovf = take(4ull * S_), o_btau = take(4ull * S_), o_bcap = take(4ull * S_),
+                   o_grp = take(sizeof(Group) * (ix_->t_all + 1)), o_ctrl = take(sizeof(Control)),
+                   o_work = take(8), o_stats = take(8 * 4), o_adm = take(sizeof(AdmitRec) * S_);
+    hipError_t e = hipMalloc(&dev_, used);
+    if (e != hipSuccess) { dev_ = nullptr; return e; }
+    char *b = (char *)dev_;
+    qb_.queries = (const uint64_t *)(b + o_q);
+    qb_.k = (const uint32_t *)(b + o_k);
+    qb_.tau = (uint32_t *)(b + o_tau);
+    qb_.count = (uint32_t *)(b + o_cnt);
+    qb_.cap = (const uint32_t *)(b + o_cap);
+    qb_.buf_off = (const uint64_t *)(b + o_boff);
+    qb_.hist = (uint32_t *)(b + o_hist);
+    qb_.nq = S_;
+    qb_.bits = ix_->bits;
+    t_ = (uint32_t *)(b + o_t);
+    out_ids_ = (uint64_t *)(b + o_oi);
+    out_dists_ = (uint64_t *)(b + o_od);
+    active_ = (uint32_t *)(b + o_act);
+    active_tmp_ = (uint32_t *)(b + o_tmp);
+    next_t_ = (uint32_t *)(b + o_nt);
+    new_slots_ = (uint32_t *)(b + o_new);
+    done_list_ = (uint32_t *)(b + o_done);
+    ovf_list_ = (uint32_t *)(b + o_ovf);
+    bound_tau_ = (uint32_t *)(b + o_btau);
+    bound_cap_ = (uint32_t *)(b + o_bcap);
+    groups_ = (Group *)(b + o_grp);
+    ctrl_ = (Control *)(b + o_ctrl);
+    work_ = (unsigned long long *)(b + o_work);
+    stats_ = (unsigned long long *)(b + o_stats);
+    admit_dev_ = (AdmitRec *)(b + o_adm);
+
+    const uint64_t pe = pool_entries ? pool_entries : 1;
+    e = hipMalloc((void **)&pool_mem_, pe * 8);
+    if (e != hipSuccess) { pool_mem_ = nullptr; return e; }
+    pool_.reset(pe);
+    qb_.buf = pool_mem_;
+    e = hipHostMalloc((void **)&ctrl_host_, sizeof(Control), 0);
+    if (e != hipSuccess) { ctrl_host_ = nullptr; return e; }
+    std::memset(ctrl_host_, 0, sizeof(Control));
+    if ((e = hipEventCreate(&ev_a_)) != hipSuccess || (e = hipEventCreate(&ev_b_)) != hipSuccess) return e;
+    // zeroed control block, counters and statistics
+    if ((e = fill_u32((uint32_t *)ctrl_, sizeof(Control) / 4, 0u, s_)) != hipSuccess) return e;
+    if ((e = fill_u64((uint64_t *)work_, 1, 0ull, s_)) != hipSuccess) return e;
+    if ((e = fill_u64((uint64_t *)stats_, 4, 0ull, s_)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
+    free_slots_.resize(S_);
+    for (uint32_t i = 0; i < S_; ++i) free_slots_[i] = S_ - 1 - i;
+    slot_info_.assign(S_, SlotInfo());
+    return hipSuccess;
+}
+
+void Engine::fill_args(MihArgs &A) const
+{
+    A.tables = ix_->tables_dev;
+    A.codes = ix_->codes;
+    A.n = ix_->n;
+    A.W = ix_->W;
+    A.m = ix_->m;
+    A.bits = ix_->bits;
+    A.t_all = ix_->t_all;
+    A.sorted = ix_->table_mode == MIH_TABLE_SORTED;
+    A.inline_codes = ix_->codes_mode == MIH_CODES_INLINE;
+    A.chunk = ix_->tuning.chunk;
+    A.J = ix_->tuning.probes_per_lane;
+    A.qb = qb_;
+    A.t = t_;
+    A.out_ids = out_ids_;
+    A.out_dists = out_dists_;
+    A.active = active_;
+    A.active_tmp = active_tmp_;
+    A.next_t = next_t_;
+    A.new_slots = new_slots_;
+    A.done_list = done_list_;
+    A.ovf_list = ovf_list_;
+    A.groups = groups_;
+    A.ctrl = ctrl_;
+    A.work = work_;
+    A.stats = stats_;
+}
+
+uint64_t Engine::submit(const uint64_t *queries, uint32_t nq, const uint32_t *k,
+                        const uint64_t *row_off, uint32_t *out_ids, uint32_t *out_dists)
+{
+    const uint64_t ticket = next_ticket_++;
+    Req r;
+    r.queries = queries;
+    r.nq = nq;
+    r.k.assign(k, k + nq);
+    r.row_off.assign(row_off, row_off + nq);
+    r.out_ids = out_ids;
+    r.out_dists = out_dists;
+    reqs_.emplace(ticket, std::move(r));
+    pending_.push_back(ticket);
+    return ticket;
+}
+
+uint32_t Engine::pending_queries() const
+{
+    uint32_t p = 0;
+    for (uint64_t t : pending_) {
+        auto it = reqs_.find(t);
+        if (it != reqs_.end()) p += it->second.nq - it->second.next;
+    }
+    return p;
+}
+
+hipError_t Engine::admit()
+{
+    std::vector<AdmitRec> recs;
+    const uint32_t W = ix_->W;
+    // queries that overflowed come back first; they keep their slot
+    while (!reruns_.empty()) {
+        Rerun rr = reruns_.front();
+        uint64_t off;
+        if (rr.cap > pool_.size() && pool_.free_total() == pool_.size() && recs.empty()) {
+            // the exact capacity exceeds the pool: grow it while it is unused
+            (void)hipStreamSynchronize(s_);
+            uint64_t *np = nullptr;
+            const uint64_t ns = std::max<uint64_t>(rr.cap, pool_.size() * 2);
+            hipError_t e = hipMalloc((void **)&np, ns * 8);
+            if (e != hipSuccess) return e;
+            (void)hipFree(pool_mem_);
+            pool_mem_ = np;
+            qb_.buf = np;
+            pool_.reset(ns);
+            graph_tuning_version_ = ~0u;   // kernel arguments changed
+        }
+        if (!pool_.alloc(rr.cap, off)) break;
+        SlotInfo &si = slot_info_[rr.slot];
+        const Req &r = reqs_.at(si.ticket);
+        si.buf_off = off;
+        si.buf_len = rr.cap;
+        AdmitRec a;
+        a.slot = rr.slot;
+        a.k = r.k[si.query];
+        a.cap = rr.cap;
+        a.tau0 = rr.tau0;
+        a.buf_off = off;
+        a.query = (uint64_t)(uintptr_t)(qb_.queries + (uint64_t)rr.slot * W);
+        a.out_ids = (uint64_t)(uintptr_t)(r.out_ids + r.row_off[si.query]);
+        a.out_dists = (uint64_t)(uintptr_t)(r.out_dists + r.row_off[si.query]);
+        recs.push_back(a);
+        reruns_.pop_front();
+    }
+    while (reruns_.empty() && !pending_.empty()) {
+        const uint64_t ticket = pending_.front();
+        Req &r = reqs_.at(ticket);
+        bool stalled = false;
+        while (r.next < r.nq) {
+            const uint32_t i = r.next;
+            const uint32_t k = r.k[i];
+            if (k == 0) {   // nothing to search and nothing to write
+                r.next++;
+                r.done++;
+                continue;
+            }
+            uint64_t off;
+            const uint32_t cap = search_capacity(k);
+            if (free_slots_.empty() || !pool_.alloc(cap, off)) { stalled = true; break; }
+            const uint32_t slot = free_slots_.back();
+            free_slots_.pop_back();
+            slot_info_[slot] = SlotInfo{ticket, i, off, cap};
+            AdmitRec a;
+            a.slot = slot;
+            a.k = k;
+            a.cap = cap;
+            a.tau0 = ix_->bits;
+            a.buf_off = off;
+            a.query = (uint64_t)(uintptr_t)(r.queries + (uint64_t)i * W);
+            a.out_ids = (uint64_t)(uintptr_t)(r.out_ids + r.row_off[i]);
+            a.out_dists = (uint64_t)(uintptr_t)(r.out_dists + r.row_off[i]);
+            recs.push_back(a);
+            r.next++;
+            in_flight_++;
+        }
+        if (stalled) break;
+        pending_.pop_front();
+    }
+    if (recs.empty()) return hipSuccess;
+    hipError_t e = sync_copy(admit_dev_, recs.data(), sizeof(AdmitRec) * recs.size(),
+                             hipMemcpyHostToDevice, s_);
+    if (e != hipSuccess) return e;
+    MihArgs A;
+    fill_args(A);
+    return mih_admit(A, admit_dev_, (uint32_t)recs.size(), s_);
+}
+
+hipError_t Engine::capture_graph()
+{
+    if (graph_exec_) { (void)hipGraphExecDestroy(graph_exec_); graph_exec_ = nullptr; }
+    if (graph_) { (void)hipGraphDestroy(graph_); graph_ = nullptr; }
+    MihArgs A;
+    fill_args(A);
+    uint32_t per_cu = (uint32_t)mih_round_occupancy(A.W, A.sorted, A.inline_codes, A.J);
+    if (ix_->tuning.blocks_per_cu && ix_->tuning.blocks_per_cu < per_cu) per_cu = ix_->tuning.blocks_per_cu;
+    round_grid_ = cu_count() * per_cu;
+    if (!use_graph_) {
+        graph_tuning_version_ = ix_->tuning_version;
+        return hipSuccess;
+    }
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = mih_regroup(A, cs);
+        if (e1 == hipSuccess) e1 = mih_round(A, round_grid_, cs);
+        if (e1 == hipSuccess) e1 = mih_advance(A, S_, cs);
+        if (e1 == hipSuccess)
+            e1 = hipMemcpyAsync(ctrl_host_, ctrl_, sizeof(Control), hipMemcpyDeviceToHost, cs);
+        e = hipStreamEndCapture(cs, &graph_);
+        if (e1 != hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        // fall back to direct launches
+        (void)hipGetLastError();
+        if (graph_) { (void)hipGraphDestroy(graph_); graph_ = nullptr; }
+        graph_exec_ = nullptr;
+        use_graph_ = false;
+    }
+    graph_tuning_version_ = ix_->tuning_version;
+    return hipSuccess;
+}
+
+hipError_t Engine::run_round()
+{
+    hipError_t e;
+    if (graph_tuning_version_ != ix_->tuning_version || (use_graph_ && !graph_exec_)) {
+        if ((e = capture_graph()) != hipSuccess) return e;
+    }
+    if (use_graph_ && graph_exec_) {
+        // the events bracket the whole replay; the regroup and advance
+        // kernels around the search kernel take microseconds
+        if ((e = hipEventRecord(ev_a_, s_)) != hipSuccess) return e;
+        if ((e = hipGraphLaunch(graph_exec_, s_)) != hipSuccess) return e;
+        if ((e = hipEventRecord(ev_b_, s_)) != hipSuccess) return e;
+    } else {
+        MihArgs A;
+        fill_args(A);
+        if ((e = mih_regroup(A, s_)) != hipSuccess) return e;
+        if ((e = hipEventRecord(ev_a_, s_)) != hipSuccess) return e;
+        if ((e = mih_round(A, round_grid_, s_)) != hipSuccess) return e;
+        if ((e = hipEventRecord(ev_b_, s_)) != hipSuccess) return e;
+        if ((e = mih_advance(A, S_, s_)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(ctrl_host_, ctrl_, sizeof(Control), hipMemcpyDeviceToHost, s_)) != hipSuccess)
+            return e;
+    }
+    if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, ev_a_, ev_b_) == hipSuccess) stats_host_.search_kernel_ms += ms;
+    else (void)hipGetLastError();
+    stats_host_.search_launches++;
+    stats_host_.rounds++;
+    return hipSuccess;
+}
+
+hipError_t Engine::step(std::vector<uint64_t> &completed)
+{
+    hipError_t e = admit();
+    if (e != hipSuccess) return e;
+    // requests that needed no search (every k = 0) are complete already
+    for (auto it = reqs_.begin(); it != reqs_.end();) {
+        if (it->second.next == it->second.nq && it->second.done == it->second.nq) {
+            completed.push_back(it->first);
+            it = reqs_.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    if (in_flight_ == 0) return hipSuccess;
+    if ((e = run_round()) != hipSuccess) return e;
+    const uint32_t n_done = ctrl_host_->n_done, n_ovf = ctrl_host_->n_ovf;
+    std::vector<uint32_t> done(n_done), ovf(n_ovf);
+    if (n_done) {
+        if ((e = sync_copy(done.data(), done_list_, 4ull * n_done, hipMemcpyDeviceToHost, s_)) != hipSuccess)
+            return e;
+        if ((e = finalize_list(qb_, done_list_, n_done, out_ids_, out_dists_, s_)) != hipSuccess) return e;
+    }
+    if (n_ovf) {
+        if ((e = sync_copy(ovf.data(), ovf_list_, 4ull * n_ovf, hipMemcpyDeviceToHost, s_)) != hipSuccess)
+            return e;
+        if ((e = exact_bounds(qb_, ovf_list_, n_ovf, bound_tau_, bound_cap_, s_)) != hipSuccess) return e;
+        std::vector<uint32_t> tau(n_ovf), cap(n_ovf);
+        if ((e = sync_copy(tau.data(), bound_tau_, 4ull * n_ovf, hipMemcpyDeviceToHost, s_)) != hipSuccess)
+            return e;
+        if ((e = sync_copy(cap.data(), bound_cap_, 4ull * n_ovf, hipMemcpyDeviceToHost, s_)) != hipSuccess)
+            return e;
+        for (uint32_t i = 0; i < n_ovf; ++i) {
+            SlotInfo &si = slot_info_[ovf[i]];
+            pool_.release(si.buf_off, si.buf_len);
+            si.buf_len = 0;
+            reruns_.push_back(Rerun{ovf[i], tau[i], std::max<uint32_t>(cap[i], 1u)});
+            stats_host_.reruns++;
+        }
+    }
+    if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
+    for (uint32_t q : done) {
+        SlotInfo &si = slot_info_[q];
+        auto it = reqs_.find(si.ticket);
+        pool_.release(si.buf_off, si.buf_len);
+        si.buf_len = 0;
+        free_slots_.push_back(q);
+        in_flight_--;
+        if (it == reqs_.end()) continue;
+        Req &r = it->second;
+        r.done++;
+        if (r.done == r.nq && r.next == r.nq) {
+            completed.push_back(it->first);
+            reqs_.erase(it);
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t Engine::reset_stats()
+{
+    stats_host_ = EngineStats();
+    return fill_u64((uint64_t *)stats_, 4, 0ull, s_);
+}
+
+hipError_t Engine::read_stats(EngineStats &out)
+{
+    unsigned long long st[4] = {0, 0, 0, 0};
+    hipError_t e = sync_copy(st, stats_, sizeof(st), hipMemcpyDeviceToHost, s_);
+    if (e != hipSuccess) return e;
+    out = stats_host_;
+    out.probes = st[0];
+    out.candidates = st[1];
+    out.steps = st[2];
+    out.appended = st[3];
+    return hipSuccess;
+}
+
+}  // namespace mih

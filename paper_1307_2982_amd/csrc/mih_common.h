@@ -252,6 +252,10 @@ struct FinalArgs {
 };
 hipError_t find_overflow(const FinalArgs &a, hipStream_t s);
 hipError_t finalize_topk(const FinalArgs &a, hipStream_t s);
+// Finalize the listed queries; out_ids[q] / out_dists[q] are the device
+// addresses of query q's output rows.
+hipError_t finalize_list(const QueryBatch &qb, const uint32_t *list, uint32_t nlist,
+                         const uint64_t *out_ids, const uint64_t *out_dists, hipStream_t s);
 // For re-runs: per listed query, exact tau and the capacity it needs.
 hipError_t exact_bounds(const QueryBatch &qb, const uint32_t *list, uint32_t nlist,
                         uint32_t *tau_out, uint32_t *cap_out, hipStream_t s);

@@ -12,14 +12,28 @@ struct Group {
     uint32_t t;           // step to process
     uint32_t count;       // queries in the group
     uint32_t ipq;         // work items per query: ceil(C(s_a, r') / chunk)
-    uint32_t slot_start;  // first slot of the group in the active list
+    uint32_t slot_start;  // first position of the group in the active list
     uint64_t item_start;  // first work item of the group
 };
 
+// Device-resident control block of a search engine.
 struct Control {
-    uint32_t n_active;
+    uint32_t n_active;    // queries in the active list of the current round
     uint32_t n_groups;
     uint64_t total_items;
+    uint32_t n_new;       // queries admitted since the last regroup
+    uint32_t n_done;      // queries finished by the last advance
+    uint32_t n_ovf;       // queries finished with an overflowed buffer
+    uint32_t pad;
+};
+
+// One admitted query: its slot and the state it starts from.
+struct AdmitRec {
+    uint32_t slot, k, cap, tau0;
+    uint64_t buf_off;     // first buffer entry of the slot
+    uint64_t query;       // device address of the query's words
+    uint64_t out_ids;     // device address of the query's output row
+    uint64_t out_dists;
 };
 
 struct MihArgs {
@@ -32,11 +46,18 @@ struct MihArgs {
     uint32_t inline_codes;    // INLINE codes
     uint32_t chunk;           // masks per work item (multiple of 64 J)
     uint32_t J;               // masks per lane per iteration: 4, 8 or 16
-    QueryBatch qb;
-    uint32_t *t;              // [nq] current step of each query
-    const uint32_t *active;   // [n_active] query of each slot, grouped by step
-    const Group *groups;
-    const Control *ctrl;
+    QueryBatch qb;            // per-slot state (qb.queries is slot storage)
+    uint32_t *t;              // [slots] current step of each query
+    uint64_t *out_ids;        // [slots] output row of each query
+    uint64_t *out_dists;      // [slots]
+    uint32_t *active;         // [slots] active list, grouped by step
+    uint32_t *active_tmp;     // [slots] scratch of the regroup
+    uint32_t *next_t;         // [slots] next step per active entry, or ~0
+    uint32_t *new_slots;      // [slots] queries admitted since the last regroup
+    uint32_t *done_list;      // [slots]
+    uint32_t *ovf_list;       // [slots]
+    Group *groups;            // [t_all + 1]
+    Control *ctrl;
     unsigned long long *work; // work-item counter
     unsigned long long *stats;// [2] probes, candidates
 };
@@ -44,10 +65,11 @@ struct MihArgs {
 hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s);
 int mih_round_occupancy(uint32_t W, bool sorted, bool inline_codes, uint32_t J);
 bool mih_probes_per_lane_ok(uint32_t J);
-// Termination tests and regrouping after a round.  nq bounds the number of
-// active slots.  A.ctrl and ctrl_out may be the same; new_active must differ
-// from A.active.
-hipError_t mih_advance(const MihArgs &A, uint32_t nq, uint32_t *next_t, uint32_t *new_active,
-                       Group *groups, Control *ctrl_out, hipStream_t s);
+// Start of a round: merge survivors and new queries into the active list.
+hipError_t mih_regroup(const MihArgs &A, hipStream_t s);
+// End of a round: termination tests; max_slots bounds the active list.
+hipError_t mih_advance(const MihArgs &A, uint32_t max_slots, hipStream_t s);
+// Admission of n queries described by rec (device memory).
+hipError_t mih_admit(const MihArgs &A, const AdmitRec *rec, uint32_t n, hipStream_t s);
 
 }  // namespace mih

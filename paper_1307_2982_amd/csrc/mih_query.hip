@@ -258,13 +258,15 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
     }
 }
 
-// Termination test after the last processed step and move to the next
-// non-empty step (a shell is empty when r' exceeds the substring length).
-__global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A, uint32_t *next_t)
+// After a round: termination test for the step each active query just
+// finished, and the next non-empty step for the others (a shell is empty
+// when r' exceeds the substring length).  Finished queries go to the done
+// list, or to the overflow list when their candidate buffer overflowed.
+__global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
 {
-    const uint32_t slot = blockIdx.x * MIH_BLOCK + threadIdx.x;
-    if (slot >= A.ctrl->n_active) return;
-    const uint32_t q = A.active[slot];
+    const uint32_t i = blockIdx.x * MIH_BLOCK + threadIdx.x;
+    if (i >= A.ctrl->n_active) return;
+    const uint32_t q = A.active[i];
     const uint32_t nb = A.qb.bits + 1;
     const uint32_t *h = A.qb.hist + (uint64_t)q * nb;
     const uint32_t k = A.qb.k[q];
@@ -283,27 +285,40 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A, 
             if (D <= tn || tn >= A.t_all) break;
         }
     }
-    if (out != 0xFFFFFFFFu) A.t[q] = out;
-    next_t[slot] = out;
+    A.next_t[i] = out;
+    if (out != 0xFFFFFFFFu) {
+        A.t[q] = out;
+        return;
+    }
+    atomicAdd(&A.stats[2], (unsigned long long)t + 1);                  // steps
+    atomicAdd(&A.stats[3], (unsigned long long)A.qb.count[q]);          // appended
+    if (A.qb.count[q] > A.qb.cap[q]) {
+        A.ovf_list[atomicAdd(&A.ctrl->n_ovf, 1u)] = q;
+    } else {
+        A.done_list[atomicAdd(&A.ctrl->n_done, 1u)] = q;
+    }
 }
 
-// Regroup the surviving queries by their next step (one workgroup).
-__global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A, const uint32_t *next_t,
-                                                           uint32_t *new_active, mih::Group *groups,
-                                                           mih::Control *ctrl_out)
+// Start of a round (one workgroup): the queries that survived the last
+// advance and the newly admitted ones (at step 0) form the active list,
+// grouped by step; the work-item numbering follows the groups.
+__global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
 {
     extern __shared__ uint32_t bins[];   // [nbins] counts, then [nbins] cursors
     __shared__ uint32_t s_active, s_groups;
     __shared__ unsigned long long s_items;
     const uint32_t tid = threadIdx.x;
     const uint32_t nbins = A.t_all + 1;
-    const uint32_t n_old = A.ctrl->n_active;
+    mih::Control *ctrl = A.ctrl;
+    const uint32_t n_old = ctrl->n_active;
+    const uint32_t n_new = ctrl->n_new;
     for (uint32_t i = tid; i < 2 * nbins; i += 1024) bins[i] = 0;
     __syncthreads();
     for (uint32_t i = tid; i < n_old; i += 1024) {
-        uint32_t nt = next_t[i];
+        uint32_t nt = A.next_t[i];
         if (nt != 0xFFFFFFFFu) atomicAdd(&bins[nt], 1u);
     }
+    if (tid == 0) atomicAdd(&bins[0], n_new);
     __syncthreads();
     if (tid == 0) {
         uint32_t slot = 0, ng = 0;
@@ -321,7 +336,7 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A, const
             G.ipq = ipq;
             G.slot_start = slot;
             G.item_start = items;
-            groups[ng++] = G;
+            A.groups[ng++] = G;
             slot += c;
             items += (uint64_t)c * ipq;
         }
@@ -331,15 +346,47 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A, const
     }
     __syncthreads();
     for (uint32_t i = tid; i < n_old; i += 1024) {
-        uint32_t nt = next_t[i];
-        if (nt != 0xFFFFFFFFu) new_active[atomicAdd(&bins[nbins + nt], 1u)] = A.active[i];
+        uint32_t nt = A.next_t[i];
+        if (nt != 0xFFFFFFFFu) A.active_tmp[atomicAdd(&bins[nbins + nt], 1u)] = A.active[i];
     }
+    for (uint32_t i = tid; i < n_new; i += 1024) A.active_tmp[atomicAdd(&bins[nbins], 1u)] = A.new_slots[i];
+    __syncthreads();
+    const uint32_t total = s_active;
+    for (uint32_t i = tid; i < total; i += 1024) A.active[i] = A.active_tmp[i];
     if (tid == 0) {
-        ctrl_out->n_active = s_active;
-        ctrl_out->n_groups = s_groups;
-        ctrl_out->total_items = s_items;
+        ctrl->n_active = total;
+        ctrl->n_groups = s_groups;
+        ctrl->total_items = s_items;
+        ctrl->n_new = 0;
+        ctrl->n_done = 0;
+        ctrl->n_ovf = 0;
         *A.work = 0;
     }
+}
+
+// Admission: per-slot state of newly admitted queries (one thread each).
+__global__ __launch_bounds__(MIH_BLOCK) void mih_admit_kernel(mih::MihArgs A, const mih::AdmitRec *rec,
+                                                              uint32_t n)
+{
+    const uint32_t i = blockIdx.x * MIH_BLOCK + threadIdx.x;
+    if (i == 0) A.ctrl->n_new = n;
+    if (i >= n) return;
+    const mih::AdmitRec r = rec[i];
+    const uint32_t q = r.slot;
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(r.query);
+    uint64_t *dst = const_cast<uint64_t *>(A.qb.queries) + (uint64_t)q * A.W;
+    for (uint32_t w = 0; w < A.W; ++w) dst[w] = src[w];
+    const_cast<uint32_t *>(A.qb.k)[q] = r.k;
+    const_cast<uint32_t *>(A.qb.cap)[q] = r.cap;
+    const_cast<uint64_t *>(A.qb.buf_off)[q] = r.buf_off;
+    A.qb.tau[q] = r.tau0;
+    A.qb.count[q] = 0;
+    A.t[q] = 0;
+    A.out_ids[q] = r.out_ids;
+    A.out_dists[q] = r.out_dists;
+    uint32_t *h = A.qb.hist + (uint64_t)q * (A.bits + 1);
+    for (uint32_t d = 0; d <= A.bits; ++d) h[d] = 0;
+    A.new_slots[i] = q;
 }
 
 // Kernel for (W, table mode, codes mode, J); J must be 4, 8 or 16.
@@ -397,15 +444,24 @@ int mih_round_occupancy(uint32_t W, bool sorted, bool inline_codes, uint32_t J)
     return blocks > 0 ? blocks : 1;
 }
 
-hipError_t mih_advance(const MihArgs &A, uint32_t nq, uint32_t *next_t, uint32_t *new_active,
-                       Group *groups, Control *ctrl_out, hipStream_t s)
+hipError_t mih_regroup(const MihArgs &A, hipStream_t s)
 {
-    if (nq == 0) return hipSuccess;
-    mih_advance_kernel<<<(nq + MIH_BLOCK - 1) / MIH_BLOCK, MIH_BLOCK, 0, s>>>(A, next_t);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const size_t lds = sizeof(uint32_t) * 2 * (A.t_all + 1);
-    mih_regroup_kernel<<<1, 1024, lds, s>>>(A, next_t, new_active, groups, ctrl_out);
+    mih_regroup_kernel<<<1, 1024, lds, s>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t mih_advance(const MihArgs &A, uint32_t max_slots, hipStream_t s)
+{
+    if (max_slots == 0) return hipSuccess;
+    mih_advance_kernel<<<(max_slots + MIH_BLOCK - 1) / MIH_BLOCK, MIH_BLOCK, 0, s>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t mih_admit(const MihArgs &A, const AdmitRec *rec, uint32_t n, hipStream_t s)
+{
+    mih_admit_kernel<<<(n + MIH_BLOCK - 1) / MIH_BLOCK > 0 ? (n + MIH_BLOCK - 1) / MIH_BLOCK : 1,
+                       MIH_BLOCK, 0, s>>>(A, rec, n);
     return hipGetLastError();
 }
 

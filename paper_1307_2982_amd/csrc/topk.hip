@@ -31,16 +31,15 @@ __device__ __forceinline__ void kth_distance(const QueryBatch &qb, uint32_t q, u
     }
 }
 
-__global__ __launch_bounds__(MIH_BLOCK) void finalize_kernel(mih::FinalArgs a)
+// One workgroup finalizes query q into oid[0..k), odist[0..k).
+__device__ void finalize_one(const QueryBatch &qb, uint32_t q, uint32_t *oid, uint32_t *odist)
 {
     __shared__ uint64_t sel[MIH_K_MAX];
     __shared__ uint32_t digit_hist[256];
     __shared__ uint32_t s_kk, s_D, s_below, s_at_D, s_prefix, s_pmask, s_remaining, s_count;
-    const uint32_t q = blockIdx.x, tid = threadIdx.x;
-    const QueryBatch &qb = a.qb;
+    const uint32_t tid = threadIdx.x;
     const uint32_t k = qb.k[q];
     if (k == 0) return;
-    const uint64_t off = a.row_off[q];
     if (tid == 0) {
         uint32_t kk, D, below, at_D;
         kth_distance(qb, q, kk, D, below, at_D);
@@ -108,13 +107,30 @@ __global__ __launch_bounds__(MIH_BLOCK) void finalize_kernel(mih::FinalArgs a)
     }
     for (uint32_t r = tid; r < k; r += MIH_BLOCK) {
         if (r < kk) {
-            a.out_ids[off + r] = (uint32_t)sel[r];
-            a.out_dists[off + r] = (uint32_t)(sel[r] >> 32);
+            oid[r] = (uint32_t)sel[r];
+            odist[r] = (uint32_t)(sel[r] >> 32);
         } else {
-            a.out_ids[off + r] = MIH_SENTINEL;
-            a.out_dists[off + r] = MIH_SENTINEL;
+            oid[r] = MIH_SENTINEL;
+            odist[r] = MIH_SENTINEL;
         }
     }
+}
+
+__global__ __launch_bounds__(MIH_BLOCK) void finalize_kernel(mih::FinalArgs a)
+{
+    const uint32_t q = blockIdx.x;
+    const uint64_t off = a.row_off[q];
+    finalize_one(a.qb, q, a.out_ids + off, a.out_dists + off);
+}
+
+// Queries of a list, each with its own output row (device addresses).
+__global__ __launch_bounds__(MIH_BLOCK) void finalize_list_kernel(QueryBatch qb, const uint32_t *list,
+                                                                  const uint64_t *out_ids,
+                                                                  const uint64_t *out_dists)
+{
+    const uint32_t q = list[blockIdx.x];
+    finalize_one(qb, q, reinterpret_cast<uint32_t *>(out_ids[q]),
+                 reinterpret_cast<uint32_t *>(out_dists[q]));
 }
 
 __global__ __launch_bounds__(MIH_BLOCK) void find_overflow_kernel(QueryBatch qb, uint32_t *list,
@@ -157,6 +173,14 @@ hipError_t finalize_topk(const FinalArgs &a, hipStream_t s)
 {
     if (a.qb.nq == 0) return hipSuccess;
     finalize_kernel<<<a.qb.nq, MIH_BLOCK, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t finalize_list(const QueryBatch &qb, const uint32_t *list, uint32_t nlist,
+                         const uint64_t *out_ids, const uint64_t *out_dists, hipStream_t s)
+{
+    if (nlist == 0) return hipSuccess;
+    finalize_list_kernel<<<nlist, MIH_BLOCK, 0, s>>>(qb, list, out_ids, out_dists);
     return hipGetLastError();
 }
 
