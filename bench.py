@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4])
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--n", type=int, default=None, help="override the database size")
     ap.add_argument("--nq", type=int, default=None, help="override the number of queries")
     ap.add_argument("--k", type=int, default=None, help="override k (single value)")
@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="wall-time budget of the CPU oracle sample")
     ap.add_argument("--threads", type=int, default=None, help="host threads for generation/oracle")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch tuning")
+    ap.add_argument("--autotune-sample", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-warmup", type=int, default=30)
@@ -217,7 +219,10 @@ def main():
     log(f"workload {cfg['name']}: n={n} bits={bits} m={m} nq={nq} k={ks} threads={threads}")
 
     t0 = time.time()
-    codes = datagen.db_codes(kind, n, bits, threads=threads)
+    # large clustered sets are generated on the device (bit-identical to the
+    # host generator); the host copy the oracle needs is made on demand
+    device_gen = kind == "clustered" and n >= 20_000_000
+    codes = None if device_gen else datagen.db_codes(kind, n, bits, threads=threads)
     queries = datagen.query_codes(kind, nq, bits, threads=threads)
     if mixed_k:
         kq = datagen.choice_u32(nq, ks, datagen.SEED_K)
@@ -228,7 +233,7 @@ def main():
         k_list = np.full(nq, ks[0], dtype=np.uint32)
     log(f"generated codes on the host in {time.time() - t0:.1f}s")
     t0 = time.time()
-    dc = to_device(codes)
+    dc = datagen.codes_device(kind, n, bits, datagen.SEED_DB_CLUSTERED) if device_gen else to_device(codes)
     dq = to_device(queries)
     log(f"copied to the device in {time.time() - t0:.1f}s")
 
@@ -250,6 +255,14 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {words * 8} bytes read and written")
         del a, b
+
+    # ---------------- launch tuning picked on a sample of the queries
+    tuned = None
+    if not args.no_autotune:
+        t = time.time()
+        ns = min(nq, args.autotune_sample)
+        tuned = idx.autotune(dq[:ns], k_arg if isinstance(k_arg, int) else k_arg[:ns])
+        log(f"autotuned on {ns} queries in {time.time() - t:.1f}s: {tuned}")
 
     # ---------------- multi-index hashing
     for _ in range(args.warmup):
@@ -343,7 +356,11 @@ def main():
     # ---------------- serving loop (continuous batching)
     serving = None
     if not args.no_serve:
+        # the serving streams carry k from {1,10,100,1000} (1e9 x 64-bit) or
+        # the configuration's own k values
         serve_k = datagen.CONFIGS[args.config]["ks"] if args.config != 4 else (1, 10, 100, 1000)
+        if args.config == 5:
+            serve_k = (1, 10, 100)
         serving = serve_bench(mih, idx, kind, bits, serve_k, args, log)
 
     # ---------------- linear scan
@@ -384,6 +401,10 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
+        if codes is None:
+            t = time.time()
+            codes = dc.cpu().numpy().view(np.uint64)
+            log(f"copied the codes to the host for the oracle in {time.time() - t:.1f}s")
         gi = ids.reshape(-1).cpu().numpy().view(np.uint32)
         gd = dists.reshape(-1).cpu().numpy().view(np.uint32)
         off = np.concatenate([[0], np.cumsum(k_list.astype(np.int64))])
@@ -443,6 +464,7 @@ def main():
                    "mih_vs_linscan_all": lin["parity_with_mih"] if lin else None},
         "mih_step_ms": [round(x, 2) for x in step_ms],
         "tuning": idx.get_tuning(),
+        "autotuned": tuned is not None,
         "tuning_sweep": sweep,
         "m_sweep": m_sweep,
         "mih_stats": {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in stats[-1].items()},

@@ -34,14 +34,82 @@ SEED_ARRIVALS = 7
 SEED_SIZES = 8
 
 
+_DEV_SO = os.path.join(_HERE, "libdatagen_dev.so")
+_dev_handle = None
+
+
 def build(force: bool = True) -> str:
-    """Compile ``gen.c`` into ``libdatagen.so`` (host code, gcc)."""
+    """Compile ``gen.c`` into ``libdatagen.so`` (gcc) and ``gen_device.hip``
+    into ``libdatagen_dev.so`` (hipcc, gfx950)."""
     if force or not os.path.exists(_SO):
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
                os.path.join(_HERE, "gen.c"), "-o", _SO + ".tmp"]
         subprocess.run(cmd, check=True)
         os.replace(_SO + ".tmp", _SO)
+    if force or not os.path.exists(_DEV_SO):
+        hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc"
+        cmd = [hipcc, "--offload-arch=gfx950", "-O3", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               os.path.join(_HERE, "gen_device.hip"), "-o", _DEV_SO + ".tmp"]
+        subprocess.run(cmd, check=True, capture_output=True)
+        os.replace(_DEV_SO + ".tmp", _DEV_SO)
     return _SO
+
+
+def _dev_lib():
+    """The device generators (load after torch, which owns the HIP runtime)."""
+    global _dev_handle
+    if _dev_handle is None:
+        import torch  # noqa: F401  (the HIP runtime torch has loaded is shared)
+        if not os.path.exists(_DEV_SO):
+            build(force=False)
+        L = ctypes.CDLL(_DEV_SO)
+        u64, u32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
+        L.dg_dev_uniform.argtypes = [vp, u64, u32, u64, u64, vp]
+        L.dg_dev_points.argtypes = [vp, u64, u64, u64, vp, vp]
+        L.dg_dev_pack.argtypes = [vp, vp, u64, u32, vp]
+        for f in (L.dg_dev_uniform, L.dg_dev_points, L.dg_dev_pack):
+            f.restype = ctypes.c_int
+        _dev_handle = L
+    return _dev_handle
+
+
+def codes_device(kind: str, n: int, bits: int, seed: int, first_row: int = 0,
+                 chunk: int = 1 << 22):
+    """The same rows as uniform_codes / clustered_codes, generated on cuda:0
+    into an int64 tensor [n, bits/64].  Clustered rows go through an exact
+    fp64 matrix product (see gen_device.hip)."""
+    import torch
+    words = _check_bits(bits)
+    L = _dev_lib()
+    out = torch.empty((n, words), dtype=torch.int64, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if n == 0:
+        return out
+    if kind == "uniform":
+        rc = L.dg_dev_uniform(out.data_ptr(), n, words, seed, first_row, stream)
+        if rc:
+            raise RuntimeError(f"dg_dev_uniform failed ({rc})")
+        return out
+    if kind != "clustered":
+        raise ValueError(kind)
+    mu, w = clustered_params(bits)
+    mu_d = torch.from_numpy(mu).cuda()
+    wt_d = torch.from_numpy(w.T.astype(np.float64)).cuda().contiguous()   # [128, bits]
+    for p0 in range(0, n, chunk):
+        m = min(chunk, n - p0)
+        x = torch.empty((m, 128), dtype=torch.float64, device="cuda")
+        rc = L.dg_dev_points(x.data_ptr(), m, seed, first_row + p0, mu_d.data_ptr(), stream)
+        if rc:
+            raise RuntimeError(f"dg_dev_points failed ({rc})")
+        dots = torch.matmul(x, wt_d)
+        rc = L.dg_dev_pack(out[p0:p0 + m].data_ptr(), dots.data_ptr(), m, bits, stream)
+        if rc:
+            raise RuntimeError(f"dg_dev_pack failed ({rc})")
+        del x, dots
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
 
 
 def _lib():

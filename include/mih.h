@@ -205,6 +205,14 @@ mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
  * range.  Not thread-safe with concurrent mih_knn calls on the same index. */
 mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning);
 
+/* Time mih_knn over a grid of tunings (probes_per_lane 4, 8, 16; chunk of
+ * 8, 32 or 128 times 64 * probes_per_lane; all workgroups that fit) on the
+ * given sample of queries, keep the fastest in the index and write it to
+ * *chosen (may be NULL).  Results do not depend on the tuning, so the
+ * sample only has to look like the real queries.  Arguments as mih_knn. */
+mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
+                        const uint32_t *k_per_query, void *stream, mih_tuning *chosen);
+
 /* ---- Serving: continuous batching over a built index ------------------
  *
  * A server keeps per-query search state for up to max_queries queries

@@ -84,7 +84,7 @@ class Tuning(ctypes.Structure):
 
 EXPORTED = ["mih_build", "mih_knn", "mih_knn_ex", "linscan_knn", "linscan_knn_ex", "mih_free",
             "mih_status_str", "mih_index_get_info", "mih_index_table", "mih_get_tuning",
-            "mih_set_tuning", "mih_server_create", "mih_server_submit", "mih_server_step",
+            "mih_set_tuning", "mih_autotune", "mih_server_create", "mih_server_submit", "mih_server_step",
             "mih_server_poll", "mih_server_get_stats", "mih_server_destroy"]
 
 _lib = None
@@ -126,6 +126,8 @@ def load():
     L.mih_get_tuning.restype = i32
     L.mih_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.mih_set_tuning.restype = i32
+    L.mih_autotune.argtypes = [vp, vp, u32, u32, vp, vp, ctypes.POINTER(Tuning)]
+    L.mih_autotune.restype = i32
     L.mih_server_create.argtypes = [vp, ctypes.POINTER(ServerOpts), vp, ctypes.POINTER(vp)]
     L.mih_server_create.restype = i32
     L.mih_server_submit.argtypes = [vp, vp, u32, u32, vp, vp, vp, ctypes.POINTER(u64)]
@@ -223,6 +225,17 @@ class Index:
     def set_tuning(self, probes_per_lane: int, chunk: int, blocks_per_cu: int = 0):
         t = Tuning(probes_per_lane, chunk, blocks_per_cu)
         _check(load().mih_set_tuning(self._h, ctypes.byref(t)), "mih_set_tuning")
+
+    def autotune(self, queries: torch.Tensor, k) -> dict:
+        """Pick the fastest launch tuning on a sample of queries (mih_autotune)."""
+        queries = _codes_arg(queries, "queries")
+        nq = queries.shape[0]
+        kk, kt, _ = _k_arg(k, nq, queries.device)
+        t = Tuning()
+        _check(load().mih_autotune(self._h, queries.data_ptr(), nq, kk,
+                                   kt.data_ptr() if kt is not None else None, _stream(),
+                                   ctypes.byref(t)), "mih_autotune")
+        return t.as_dict()
 
     def table(self, j: int) -> dict:
         """Copies of table j's device arrays (as CPU tensors), for inspection."""

@@ -813,3 +813,44 @@ mih_status mih_server_get_stats(mih_server *srv, mih_server_stats *st)
 void mih_server_destroy(mih_server *srv) { delete srv; }
 
 }  // extern "C"
+
+// ============================================================== autotuner
+
+extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
+                                   const uint32_t *k_per_query, void *stream, mih_tuning *chosen)
+{
+    if (!idx) return MIH_ERR_INVALID;
+    if (nq == 0) {
+        if (chosen) *chosen = idx->tuning;
+        return MIH_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint32_t> kv;
+    MIH_TRY_STATUS(read_k(nq, k, k_per_query, s, kv));
+    uint64_t total = 0;
+    for (uint32_t v : kv) total += v;
+    Scratch out;
+    MIH_TRY(out.ensure(8 * (total ? total : 1)));
+    uint32_t *oi = (uint32_t *)out.ptr, *od = oi + total;
+    const mih_tuning start = idx->tuning;
+    mih_tuning best = start;
+    double best_ms = 1e300;
+    // warm-up: first call sizes the engine and faults in the tables' pages
+    mih_status st = mih_knn(idx, queries, nq, k, k_per_query, oi, od, stream);
+    for (uint32_t J : {4u, 8u, 16u}) {
+        for (uint32_t mult : {8u, 32u, 128u}) {
+            if (st != MIH_OK) break;
+            mih_tuning t = {J, 64 * J * mult, 0};
+            if ((st = mih_set_tuning(idx, &t)) != MIH_OK) break;
+            auto t0 = clk::now();
+            st = mih_knn(idx, queries, nq, k, k_per_query, oi, od, stream);
+            const double ms = ms_since(t0);
+            if (st == MIH_OK && ms < best_ms) { best_ms = ms; best = t; }
+        }
+    }
+    mih_status st2 = mih_set_tuning(idx, st == MIH_OK ? &best : &start);
+    out.release();
+    if (st != MIH_OK) return st;
+    if (chosen) *chosen = best;
+    return st2;
+}
