@@ -313,10 +313,11 @@ def main():
     if args.sweep:
         base_t = idx.get_tuning()
         sweep = []
-        for J in (4, 8, 16):
-            for chunk in (64 * J * 2, 64 * J * 8, 64 * J * 32):
-                for bpc in (0, 2):
-                    idx.set_tuning(J, chunk, bpc)
+        for occ in ((0, 1) if info["table_mode"] == "direct" else (0,)):
+          for J in (4, 8, 16):
+            for chunk in (64 * J * 8, 64 * J * 32, 64 * J * 128):
+                for bpc in (0,):
+                    idx.set_tuning(J, chunk, bpc, occ)
                     idx.knn(dq, k_arg)
                     torch.cuda.synchronize()
                     t = time.perf_counter()
@@ -325,10 +326,12 @@ def main():
                     ms = (time.perf_counter() - t) * 1e3
                     same = bool(torch.equal(si, ids) and torch.equal(sd, dists))
                     sweep.append({"probes_per_lane": J, "chunk": chunk, "blocks_per_cu": bpc,
+                                  "occupancy_filter": occ,
                                   "ms": round(ms, 2), "kernel_ms": round(sst["search_kernel_ms"], 2),
                                   "same_result": same})
-                    log(f"tuning J={J} chunk={chunk} bpc={bpc}: {ms:.1f} ms same={same}")
-        idx.set_tuning(base_t["probes_per_lane"], base_t["chunk"], base_t["blocks_per_cu"])
+                    log(f"tuning occ={occ} J={J} chunk={chunk}: {ms:.1f} ms same={same}")
+        idx.set_tuning(base_t["probes_per_lane"], base_t["chunk"], base_t["blocks_per_cu"],
+                       base_t["occupancy_filter"])
 
     m_sweep = None
     if args.m_sweep:

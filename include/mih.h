@@ -103,7 +103,10 @@ typedef struct mih_table_view {
     const uint32_t *dir;         /* SORTED: [2^dir_bits + 1], else NULL     */
     const uint32_t *ids;         /* [n] ids in bucket order                 */
     const uint64_t *codes;       /* INLINE: [n][bits/64], else NULL         */
-    uint32_t len, start, dir_bits;
+    uint32_t len, start, dir_bits, pad;
+    const uint32_t *occupancy;   /* DIRECT: [max(2^len / 32, 1)] words, bit
+                                    v % 32 of word v / 32 = [bucket v is
+                                    non-empty]; else NULL                   */
 } mih_table_view;
 
 /* Per-call counters of the multi-index search (sums over the queries). */
@@ -196,6 +199,8 @@ typedef struct mih_tuning {
     uint32_t chunk;            /* shell masks per work item: a multiple of
                                   64 * probes_per_lane, at most 2^20           */
     uint32_t blocks_per_cu;    /* persistent workgroups per CU, 0 = all that fit */
+    uint32_t occupancy_filter; /* DIRECT tables: 1 = test a one-bit-per-bucket
+                                  occupancy map before reading the offsets   */
 } mih_tuning;
 
 /* Current tuning of an index (defaults after mih_build: 4, 8192, 0). */

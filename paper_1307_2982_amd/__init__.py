@@ -50,7 +50,8 @@ class IndexInfo(ctypes.Structure):
 class TableView(ctypes.Structure):
     _fields_ = [("offsets", ctypes.c_void_p), ("keys", ctypes.c_void_p), ("dir", ctypes.c_void_p),
                 ("ids", ctypes.c_void_p), ("codes", ctypes.c_void_p), ("len", ctypes.c_uint32),
-                ("start", ctypes.c_uint32), ("dir_bits", ctypes.c_uint32)]
+                ("start", ctypes.c_uint32), ("dir_bits", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("occupancy", ctypes.c_void_p)]
 
 
 class QueryStats(ctypes.Structure):
@@ -76,7 +77,7 @@ class ScanStats(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("probes_per_lane", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
-                ("blocks_per_cu", ctypes.c_uint32)]
+                ("blocks_per_cu", ctypes.c_uint32), ("occupancy_filter", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -222,8 +223,11 @@ class Index:
         _check(load().mih_get_tuning(self._h, ctypes.byref(t)), "mih_get_tuning")
         return t.as_dict()
 
-    def set_tuning(self, probes_per_lane: int, chunk: int, blocks_per_cu: int = 0):
-        t = Tuning(probes_per_lane, chunk, blocks_per_cu)
+    def set_tuning(self, probes_per_lane: int, chunk: int, blocks_per_cu: int = 0,
+                   occupancy_filter: int | None = None):
+        if occupancy_filter is None:
+            occupancy_filter = self.get_tuning()["occupancy_filter"]
+        t = Tuning(probes_per_lane, chunk, blocks_per_cu, occupancy_filter)
         _check(load().mih_set_tuning(self._h, ctypes.byref(t)), "mih_set_tuning")
 
     def autotune(self, queries: torch.Tensor, k) -> dict:
@@ -253,6 +257,8 @@ class Index:
             out["dir"] = _copy_device(v.dir, (1 << v.dir_bits) + 1, torch.int32)
         if v.codes:
             out["codes"] = _copy_device(v.codes, n * W, torch.int64).view(n, W)
+        if v.occupancy:
+            out["occupancy"] = _copy_device(v.occupancy, max((1 << v.len) // 32, 1), torch.int32)
         return out
 
     def knn(self, queries: torch.Tensor, k, stats: bool = False):

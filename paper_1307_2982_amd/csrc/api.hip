@@ -565,6 +565,10 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
                 if ((e = ix->alloc((void **)&off, (nb + 1) * 4)) != hipSuccess) { st = from_hip(e); break; }
                 e = mih::bucket_offsets(keys, n, 0, off, nb, (uint32_t *)tmp.ptr, s);
                 T.off = off;
+                uint32_t *occ = nullptr;
+                if (e == hipSuccess && (e = ix->alloc((void **)&occ, std::max<uint64_t>(nb / 32, 1) * 4)) == hipSuccess)
+                    e = mih::occupancy_bits(off, nb, occ, s);
+                T.occ = occ;
             } else {
                 uint32_t *skeys = nullptr, *dir = nullptr;
                 const uint64_t nb = 1ull << T.dir_bits;
@@ -595,6 +599,10 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     ti2.release();
     tmp.release();
     if (st != MIH_OK) { delete ix; return st; }
+    // the occupancy map pays off where the offsets array outgrows the caches
+    uint32_t max_len = 0;
+    for (uint32_t j = 0; j < m; ++j) max_len = std::max(max_len, ix->len[j]);
+    ix->tuning.occupancy_filter = (ix->table_mode == MIH_TABLE_DIRECT && max_len >= 26) ? 1u : 0u;
     ix->build_ms = ms_since(t0);
     *out = ix;
     return MIH_OK;
@@ -692,7 +700,7 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning)
     if (!mih::mih_probes_per_lane_ok(J)) return MIH_ERR_INVALID;
     if (tuning->chunk == 0 || tuning->chunk % (64 * J) != 0 || tuning->chunk > (1u << 20))
         return MIH_ERR_INVALID;
-    if (tuning->blocks_per_cu > 64) return MIH_ERR_INVALID;
+    if (tuning->blocks_per_cu > 64 || tuning->occupancy_filter > 1) return MIH_ERR_INVALID;
     std::lock_guard<std::mutex> lock(idx->mu);
     idx->tuning = *tuning;
     idx->tuning_version++;
@@ -711,6 +719,8 @@ mih_status mih_index_table(const mih_index *idx, uint32_t j, mih_table_view *vie
     view->len = T.len;
     view->start = T.start;
     view->dir_bits = idx->table_mode == MIH_TABLE_SORTED ? T.dir_bits : 0;
+    view->pad = 0;
+    view->occupancy = T.occ;
     return MIH_OK;
 }
 
@@ -837,15 +847,18 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
     double best_ms = 1e300;
     // warm-up: first call sizes the engine and faults in the tables' pages
     mih_status st = mih_knn(idx, queries, nq, k, k_per_query, oi, od, stream);
-    for (uint32_t J : {4u, 8u, 16u}) {
-        for (uint32_t mult : {8u, 32u, 128u}) {
-            if (st != MIH_OK) break;
-            mih_tuning t = {J, 64 * J * mult, 0};
-            if ((st = mih_set_tuning(idx, &t)) != MIH_OK) break;
-            auto t0 = clk::now();
-            st = mih_knn(idx, queries, nq, k, k_per_query, oi, od, stream);
-            const double ms = ms_since(t0);
-            if (st == MIH_OK && ms < best_ms) { best_ms = ms; best = t; }
+    const uint32_t filters = idx->table_mode == MIH_TABLE_DIRECT ? 2 : 1;
+    for (uint32_t f = 0; f < filters; ++f) {
+        for (uint32_t J : {4u, 8u, 16u}) {
+            for (uint32_t mult : {8u, 32u, 128u}) {
+                if (st != MIH_OK) break;
+                mih_tuning t = {J, 64 * J * mult, 0, f};
+                if ((st = mih_set_tuning(idx, &t)) != MIH_OK) break;
+                auto t0 = clk::now();
+                st = mih_knn(idx, queries, nq, k, k_per_query, oi, od, stream);
+                const double ms = ms_since(t0);
+                if (st == MIH_OK && ms < best_ms) { best_ms = ms; best = t; }
+            }
         }
     }
     mih_status st2 = mih_set_tuning(idx, st == MIH_OK ? &best : &start);

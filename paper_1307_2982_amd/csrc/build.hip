@@ -111,6 +111,26 @@ __global__ __launch_bounds__(MIH_BLOCK) void mark_bucket_starts(const uint32_t *
     }
 }
 
+// Bit v of occ = [bucket v is non-empty] = [off[v+1] > off[v]].
+__global__ __launch_bounds__(MIH_BLOCK) void occupancy_kernel(const uint32_t *__restrict__ off,
+                                                              uint64_t nbuckets, uint32_t *occ)
+{
+    const uint64_t nwords = (nbuckets + 31) / 32;
+    uint64_t w = (uint64_t)blockIdx.x * MIH_BLOCK + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * MIH_BLOCK;
+    for (; w < nwords; w += stride) {
+        uint32_t word = 0;
+        const uint64_t v0 = w * 32;
+        uint32_t prev = off[v0];
+        for (uint32_t b = 0; b < 32 && v0 + b < nbuckets; ++b) {
+            const uint32_t nxt = off[v0 + b + 1];
+            if (nxt > prev) word |= 1u << b;
+            prev = nxt;
+        }
+        occ[w] = word;
+    }
+}
+
 template <int W>
 __global__ __launch_bounds__(MIH_BLOCK) void gather_codes_kernel(const uint64_t *__restrict__ codes,
                                                                  const uint32_t *__restrict__ ids,
@@ -192,6 +212,12 @@ hipError_t bucket_offsets(const uint32_t *sorted_keys, uint64_t n, uint32_t shif
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return suffix_min_u32(off, off, nbuckets + 1, tmp, s);
+}
+
+hipError_t occupancy_bits(const uint32_t *off, uint64_t nbuckets, uint32_t *occ, hipStream_t s)
+{
+    occupancy_kernel<<<grid_for((nbuckets + 31) / 32), MIH_BLOCK, 0, s>>>(off, nbuckets, occ);
+    return hipGetLastError();
 }
 
 hipError_t gather_codes(const uint64_t *codes, const uint32_t *ids, uint64_t n, uint32_t W,

@@ -182,6 +182,7 @@ void Engine::fill_args(MihArgs &A) const
     A.inline_codes = ix_->codes_mode == MIH_CODES_INLINE;
     A.chunk = ix_->tuning.chunk;
     A.J = ix_->tuning.probes_per_lane;
+    A.occ_filter = ix_->tuning.occupancy_filter && ix_->table_mode == MIH_TABLE_DIRECT;
     A.qb = qb_;
     A.t = t_;
     A.out_ids = out_ids_;

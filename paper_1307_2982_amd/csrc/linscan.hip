@@ -165,16 +165,20 @@ __global__ __launch_bounds__(MIH_BLOCK) void linscan_kernel(const uint64_t *__re
                     const uint32_t q = q0 + j;
                     if (q >= qb.nq) break;
                     const uint32_t tau_j = 0x7FFFFFFFu - bias[j];
+                    uint32_t d[R];
                     bool any = false;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        uint32_t d = hamming<W>(c[r], g[j]);
-                        bool keep = valid[r] && d <= tau_j;
-                        append_candidates(qb, q, keep, d,
-                                          (uint32_t)(base + (uint64_t)r * MIH_BLOCK + tid));
-                        any |= keep;
+                        d[r] = hamming<W>(c[r], g[j]);
+                        any |= valid[r] && d[r] <= tau_j;
                     }
-                    if (__ballot(any)) tighten_tau(qb, q, tau_j);
+                    // most queries of a batch that reached the slow path have no hit
+                    if (!__ballot(any)) continue;
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        append_candidates(qb, q, valid[r] && d[r] <= tau_j, d[r],
+                                          (uint32_t)(base + (uint64_t)r * MIH_BLOCK + tid));
+                    tighten_tau(qb, q, tau_j);
                 }
             }
             tv = tv_next;

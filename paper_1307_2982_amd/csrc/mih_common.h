@@ -185,6 +185,7 @@ __device__ __forceinline__ uint32_t tighten_tau(const QueryBatch &qb, uint32_t q
 
 struct TableDev {
     const uint32_t *off;     // DIRECT: [2^len + 1]
+    const uint32_t *occ;     // DIRECT: [2^len / 32 (at least 1)] bit v: bucket v non-empty
     const uint32_t *keys;    // SORTED: [n]
     const uint32_t *dir;     // SORTED: [2^dir_bits + 1]
     const uint32_t *ids;     // [n]
@@ -226,6 +227,8 @@ hipError_t bucket_offsets(const uint32_t *sorted_keys, uint64_t n, uint32_t shif
                           uint32_t *off, uint64_t nbuckets, uint32_t *tmp, hipStream_t s);
 hipError_t gather_codes(const uint64_t *codes, const uint32_t *ids, uint64_t n, uint32_t W,
                         uint64_t *out, hipStream_t s);
+// occ[v / 32] bit v % 32 = [off[v + 1] > off[v]] for v < nbuckets.
+hipError_t occupancy_bits(const uint32_t *off, uint64_t nbuckets, uint32_t *occ, hipStream_t s);
 
 // linscan.hip
 struct LinscanArgs {

@@ -46,6 +46,7 @@ struct MihArgs {
     uint32_t inline_codes;    // INLINE codes
     uint32_t chunk;           // masks per work item (multiple of 64 J)
     uint32_t J;               // masks per lane per iteration: 4, 8 or 16
+    uint32_t occ_filter;      // DIRECT: test the occupancy bitmap before the offsets
     QueryBatch qb;            // per-slot state (qb.queries is slot storage)
     uint32_t *t;              // [slots] current step of each query
     uint64_t *out_ids;        // [slots] output row of each query

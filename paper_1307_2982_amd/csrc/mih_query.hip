@@ -99,14 +99,28 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
     for (uint32_t base = rb; base < re; base += MIH_WAVE * J) {
         const uint32_t r0 = base + lane * J;
         const uint32_t nmy = r0 < re ? (re - r0 < (uint32_t)J ? re - r0 : (uint32_t)J) : 0u;
-        uint32_t lo[J], cnt[J];
+        uint32_t lo[J], cnt[J], keys[J];
         uint32_t mask = nmy ? unrank_mask(r0, rp, s, binom) : 0u;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            keys[j] = key_q ^ mask;
+            if ((uint32_t)j + 1 < nmy && rp > 0) mask = next_mask(mask);
+        }
+        // DIRECT tables with the occupancy filter: one bit per bucket says
+        // whether it holds codes; only occupied buckets read their offsets
+        uint32_t occ_bits = ~0u;
+        if (!SORTED && A.occ_filter) {
+            occ_bits = 0;
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+                if ((uint32_t)j < nmy && ((T.occ[keys[j] >> 5] >> (keys[j] & 31)) & 1u)) occ_bits |= 1u << j;
+        }
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             cnt[j] = 0;
             lo[j] = 0;
-            if ((uint32_t)j < nmy) {
-                const uint32_t key = key_q ^ mask;
+            if ((uint32_t)j < nmy && ((occ_bits >> j) & 1u)) {
+                const uint32_t key = keys[j];
                 if (!SORTED) {
                     const uint32_t b0 = T.off[key];
                     const uint32_t b1 = T.off[(uint64_t)key + 1];
@@ -130,7 +144,6 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
                     lo[j] = l;
                     cnt[j] = e - l;
                 }
-                if ((uint32_t)j + 1 < nmy && rp > 0) mask = next_mask(mask);
             }
         }
         // stage the non-empty buckets of the wave with the running count of

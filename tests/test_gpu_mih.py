@@ -41,6 +41,11 @@ def test_build_tables_match_algorithm1(mih):
             if tmode == "direct":
                 expect = np.searchsorted(values, np.arange((1 << tab["len"]) + 1, dtype=np.uint64))
                 assert np.array_equal(tab["offsets"].numpy().view(np.uint32), expect.astype(np.uint32))
+                # occupancy map: one bit per bucket, set iff the bucket holds a code
+                occupied = np.zeros(1 << tab["len"], dtype=bool)
+                occupied[values] = True
+                bits = np.unpackbits(tab["occupancy"].numpy().view(np.uint8), bitorder="little")
+                assert np.array_equal(bits[: occupied.size].astype(bool), occupied), j
             else:
                 assert np.array_equal(tab["keys"].numpy().view(np.uint32), values.astype(np.uint32))
                 p = tab["dir_bits"]
@@ -62,6 +67,24 @@ def test_mih_uniform_64_m3_all_modes(mih, tmode, cmode):
         ids, dists = idx.knn(dq, k)
         oi, od = oracle.knn(codes, queries, k)
         assert_same(ids, dists, oi, od, f"{tmode}/{cmode} k={k}")
+
+
+@pytest.mark.parametrize("occ", [0, 1])
+def test_mih_launch_tunings_agree(mih, occ):
+    # Every launch tuning (probes per lane, chunk, occupancy filter) returns
+    # the same exact result; the filter only skips reads of empty buckets.
+    n, nq = 150_001, 60
+    codes = datagen.uniform_codes(n, 64, 51)
+    queries = datagen.uniform_codes(nq, 64, 52)
+    idx = mih.build(to_dev(codes), 3, table_mode="direct", codes_mode="inline")
+    dq = to_dev(queries)
+    oi, od = oracle.knn(codes, queries, 50)
+    for J in (4, 8, 16):
+        for chunk in (64 * J * 2, 64 * J * 32):
+            idx.set_tuning(J, chunk, 0, occ)
+            ids, dists = idx.knn(dq, 50)
+            assert_same(ids, dists, oi, od, f"occ={occ} J={J} chunk={chunk}")
+    idx.close()
 
 
 def test_mih_probe_count_equals_closed_form(mih):
