@@ -100,11 +100,12 @@ def to_device(codes: np.ndarray, chunk_rows: int = 1 << 24):
     return dev
 
 
-def counter_traffic(kernel_sources, counters_file):
+def counter_traffic(counters_file, tuning):
     """HBM bytes per launch of the search kernel from committed rocprofv3
     counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a
-    plain copy of known size), or None when the kernel source has changed
-    since the counters were taken or no counters exist for this workload."""
+    plain copy of known size), or None when the kernel source or the launch
+    tuning has changed since the counters were taken or no counters exist
+    for this workload."""
     import hashlib
     path = os.path.join(ROOT, "profiles", counters_file)
     if not os.path.exists(path):
@@ -114,6 +115,8 @@ def counter_traffic(kernel_sources, counters_file):
     for src in rec["sources"]:
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if h.hexdigest()[:16] != rec["source_sha256_16"]:
+        return None, rec
+    if any(tuning.get(k) != v for k, v in rec.get("tuning", {}).items()):
         return None, rec
     cal = rec["copy_calibration"]
     fetch = np.mean(rec["fetch_kib_per_launch"]) * cal["fetch_factor"]
@@ -294,7 +297,7 @@ def main():
     traffic = None
     if (n, bits, m, nq, tuple(ks)) == (1_000_000_000, 64, 2, 10_000, (100,)) and \
             (info["table_mode"], info["codes_mode"]) == ("direct", "inline"):
-        traffic, _ = counter_traffic(None, "mih_round_kernel_1e9x64_m2_k100_counters.json")
+        traffic, _ = counter_traffic("mih_round_kernel_1e9x64_m2_k100_counters.json", idx.get_tuning())
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
