@@ -189,6 +189,56 @@ mih_status linscan_knn_ex(const uint64_t *codes, uint64_t n, uint32_t bits,
 /* Release an index and its device memory.  NULL is ignored. */
 void mih_free(mih_index *idx);
 
+/* ---------------------------------------------------------------------
+ * r-neighbour search (Section 2.2, Algorithm 2): every database code within
+ * Hamming distance r of each query.  The number of results varies per
+ * query, so they are returned in a result object owned by the library.
+ *
+ * Results of query i are entries [offsets[i], offsets[i+1]) of ids and
+ * dists, in ascending (distance, id) order; offsets[0] = 0 and
+ * offsets[nq] = total.  The three arrays are device memory owned by the
+ * result and stay valid until mih_rnn_result_free.
+ */
+typedef struct mih_rnn_result mih_rnn_result;   /* opaque */
+
+typedef struct mih_rnn_view {
+    uint64_t total;              /* number of (query, code) results            */
+    uint32_t nq, pad;
+    const uint64_t *offsets;     /* device [nq + 1]                            */
+    const uint32_t *ids;         /* device [total] (at least one entry)        */
+    const uint32_t *dists;       /* device [total] (at least one entry)        */
+} mih_rnn_view;
+
+/* r-neighbours through the multi-index tables.  The search runs the steps of
+ * Algorithm 3 up to step r, which by Proposition 2 covers every code within
+ * distance r (it is Algorithm 2 with the tighter per-table radii of
+ * Proposition 2).
+ *   device queries    [nq][bits/64] (borrowed during the call)
+ *   r                 radius for every query, used when r_per_query is NULL
+ *   device r_per_query [nq] uint32 radii, or NULL; radii above bits mean bits
+ *   host out          receives the result (NULL on error)
+ * Errors: MIH_ERR_INVALID for a NULL index or out, misaligned or NULL
+ * queries with nq > 0; MIH_ERR_NOMEM / MIH_ERR_DEVICE as elsewhere. */
+mih_status mih_rnn(const mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t r,
+                   const uint32_t *r_per_query, void *stream, mih_rnn_result **out);
+
+/* As mih_rnn, also filling *stats (may be NULL). */
+mih_status mih_rnn_ex(const mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t r,
+                      const uint32_t *r_per_query, void *stream, mih_rnn_result **out,
+                      mih_query_stats *stats);
+
+/* r-neighbours by the linear scan: every (code, query) distance is computed.
+ * Arguments as in linscan_knn and mih_rnn. */
+mih_status linscan_rnn(const uint64_t *codes, uint64_t n, uint32_t bits,
+                       const uint64_t *queries, uint32_t nq, uint32_t r,
+                       const uint32_t *r_per_query, void *stream, mih_rnn_result **out);
+
+/* Pointers and sizes of a result.  MIH_ERR_INVALID for NULL arguments. */
+mih_status mih_rnn_result_view(const mih_rnn_result *res, mih_rnn_view *view);
+
+/* Release a result and its device memory.  NULL is ignored. */
+void mih_rnn_result_free(mih_rnn_result *res);
+
 /* Static, human-readable name of a status. */
 const char *mih_status_str(mih_status s);
 

@@ -83,7 +83,13 @@ class Tuning(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class RnnView(ctypes.Structure):
+    _fields_ = [("total", ctypes.c_uint64), ("nq", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("offsets", ctypes.c_void_p), ("ids", ctypes.c_void_p), ("dists", ctypes.c_void_p)]
+
+
 EXPORTED = ["mih_build", "mih_knn", "mih_knn_ex", "linscan_knn", "linscan_knn_ex", "mih_free",
+            "mih_rnn", "mih_rnn_ex", "linscan_rnn", "mih_rnn_result_view", "mih_rnn_result_free",
             "mih_status_str", "mih_index_get_info", "mih_index_table", "mih_get_tuning",
             "mih_set_tuning", "mih_autotune", "mih_server_create", "mih_server_submit", "mih_server_step",
             "mih_server_poll", "mih_server_get_stats", "mih_server_destroy"]
@@ -117,6 +123,16 @@ def load():
     L.linscan_knn_ex.restype = i32
     L.mih_free.argtypes = [vp]
     L.mih_free.restype = None
+    L.mih_rnn.argtypes = [vp, vp, u32, u32, vp, vp, ctypes.POINTER(vp)]
+    L.mih_rnn.restype = i32
+    L.mih_rnn_ex.argtypes = [vp, vp, u32, u32, vp, vp, ctypes.POINTER(vp), ctypes.POINTER(QueryStats)]
+    L.mih_rnn_ex.restype = i32
+    L.linscan_rnn.argtypes = [vp, u64, u32, vp, u32, u32, vp, vp, ctypes.POINTER(vp)]
+    L.linscan_rnn.restype = i32
+    L.mih_rnn_result_view.argtypes = [vp, ctypes.POINTER(RnnView)]
+    L.mih_rnn_result_view.restype = i32
+    L.mih_rnn_result_free.argtypes = [vp]
+    L.mih_rnn_result_free.restype = None
     L.mih_status_str.argtypes = [i32]
     L.mih_status_str.restype = ctypes.c_char_p
     L.mih_index_get_info.argtypes = [vp, ctypes.POINTER(IndexInfo)]
@@ -261,6 +277,25 @@ class Index:
             out["occupancy"] = _copy_device(v.occupancy, max((1 << v.len) // 32, 1), torch.int32)
         return out
 
+    def rnn(self, queries: torch.Tensor, r, stats: bool = False):
+        """Every code within distance r (an int or one radius per query) of
+        each query.  Returns (offsets, ids, dists) as device tensors: query
+        i's results are ids[offsets[i]:offsets[i+1]] in ascending (distance,
+        id) order; with stats=True a dict of search counters is appended."""
+        queries = _codes_arg(queries, "queries")
+        if queries.shape[1] != self.codes.shape[1]:
+            raise ValueError("queries and codes differ in length")
+        nq = queries.shape[0]
+        rr, rt = _r_arg(r, nq, queries.device)
+        st = QueryStats()
+        h = ctypes.c_void_p()
+        rc = load().mih_rnn_ex(self._h, queries.data_ptr() if nq else None, nq, rr,
+                               rt.data_ptr() if rt is not None else None, _stream(),
+                               ctypes.byref(h), ctypes.byref(st))
+        _check(rc, "mih_rnn")
+        out = _take_rnn(h, queries.device)
+        return (*out, st.as_dict()) if stats else out
+
     def knn(self, queries: torch.Tensor, k, stats: bool = False):
         """Exact kNN; k is an int or a per-query sequence (then rows are flat)."""
         queries = _codes_arg(queries, "queries")
@@ -289,6 +324,61 @@ def build(codes: torch.Tensor, m: int, table_mode: str = "auto", codes_mode: str
                           _stream(), ctypes.byref(h))
     _check(rc, "mih_build")
     return Index(h, codes)
+
+
+def _r_arg(r, nq: int, device):
+    """Returns (scalar r, device radius tensor or None)."""
+    if isinstance(r, int):
+        if r < 0:
+            raise ValueError("r must be non-negative")
+        return r, None
+    rt = torch.as_tensor(r, dtype=torch.int64)
+    if rt.numel() != nq:
+        raise ValueError("r_per_query must have one entry per query")
+    if (rt < 0).any():
+        raise ValueError("radii must be non-negative")
+    return 0, rt.clamp(max=0xFFFFFFFF).to(torch.int32).to(device).contiguous()
+
+
+def _take_rnn(handle, device):
+    """Device copies (offsets int64 [nq+1], ids int32, dists int32) of a
+    library-owned r-neighbour result, which is then released."""
+    L = load()
+    try:
+        v = RnnView()
+        _check(L.mih_rnn_result_view(handle, ctypes.byref(v)), "mih_rnn_result_view")
+        offsets = torch.empty(v.nq + 1, dtype=torch.int64, device=device)
+        ids = torch.empty(v.total, dtype=torch.int32, device=device)
+        dists = torch.empty(v.total, dtype=torch.int32, device=device)
+        torch.cuda.synchronize(device)
+        for dst, src, nbytes in ((offsets, v.offsets, 8 * (v.nq + 1)), (ids, v.ids, 4 * v.total),
+                                 (dists, v.dists, 4 * v.total)):
+            if nbytes:
+                rc = _hip_runtime().hipMemcpy(dst.data_ptr(), src, nbytes, 3)   # device to device
+                if rc != 0:
+                    raise RuntimeError(f"hipMemcpy failed ({rc})")
+        return offsets, ids, dists
+    finally:
+        L.mih_rnn_result_free(handle)
+
+
+def linscan_rnn(codes: torch.Tensor, queries: torch.Tensor, r):
+    """Every code within distance r of each query, by the GPU linear scan.
+    Returns (offsets, ids, dists): query i's results are ids[offsets[i]:offsets[i+1]]
+    in ascending (distance, id) order."""
+    codes = _codes_arg(codes, "codes")
+    queries = _codes_arg(queries, "queries")
+    if queries.shape[1] != codes.shape[1]:
+        raise ValueError("queries and codes differ in length")
+    n, W = codes.shape
+    nq = queries.shape[0]
+    rr, rt = _r_arg(r, nq, queries.device)
+    h = ctypes.c_void_p()
+    rc = load().linscan_rnn(codes.data_ptr() if n else None, n, 64 * W,
+                            queries.data_ptr() if nq else None, nq, rr,
+                            rt.data_ptr() if rt is not None else None, _stream(), ctypes.byref(h))
+    _check(rc, "linscan_rnn")
+    return _take_rnn(h, queries.device)
 
 
 def linscan_knn(codes: torch.Tensor, queries: torch.Tensor, k, stats: bool = False):

@@ -145,6 +145,9 @@ struct BatchSpec {
     std::vector<uint64_t> row_off;       // output offset per query
     std::vector<uint32_t> cap;           // buffer capacity per query
     const uint32_t *tau0 = nullptr;      // device, or null
+    // r-neighbour batches: hits go to this collector, query i as query
+    // row_off[i] of the request, instead of into top-k rows
+    mih::RnnCollector *rnn = nullptr;
 };
 
 struct BatchBufs {
@@ -234,6 +237,11 @@ uint32_t scan_cap(uint32_t k) { return k == 0 ? 0u : std::max<uint32_t>(4096u, 1
 
 // ============================================================== the index
 
+struct mih_rnn_result {
+    mih::RnnOut out;
+    ~mih_rnn_result() { mih::free_rnn_out(out); }
+};
+
 hipError_t mih_index::alloc(void **p, uint64_t bytes)
 {
     hipError_t e = hipMalloc(p, bytes ? bytes : 4);
@@ -289,6 +297,7 @@ mih_status rerun_linscan(const uint64_t *codes, uint64_t n, uint32_t bits, const
         rb.queries = dq;
         rb.nq = novf;
         rb.tau0 = dtau;
+        rb.rnn = b.rnn;
         rb.cap.resize(novf);
         if (download(rb.cap.data(), dcap, sizeof(uint32_t) * novf, s) != hipSuccess) { st = MIH_ERR_DEVICE; break; }
         rb.k.resize(novf);
@@ -359,8 +368,21 @@ mih_status linscan_batch(const uint64_t *codes, uint64_t n, uint32_t bits, Batch
         F.overflow_list = B.ovf_list;
         F.overflow_count = B.ovf_count;
         if (e == hipSuccess) e = mih::find_overflow(F, s);
-        if (e == hipSuccess) e = mih::finalize_topk(F, s);
+        if (e == hipSuccess && !b.rnn) e = mih::finalize_topk(F, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess && b.rnn) {
+            // every query that did not overflow holds all its hits
+            std::vector<uint32_t> cnt(b.nq), query, count;
+            std::vector<uint64_t> src;
+            e = download(cnt.data(), B.qb.count, sizeof(uint32_t) * b.nq, s);
+            for (uint32_t i = 0; i < b.nq && e == hipSuccess; ++i) {
+                if (cnt[i] > b.cap[i]) continue;
+                query.push_back((uint32_t)b.row_off[i]);
+                src.push_back(buf_off[i]);
+                count.push_back(cnt[i]);
+            }
+            if (e == hipSuccess) e = b.rnn->add(B.qb.buf, query, src, count, s);
+        }
         if (e != hipSuccess) { (void)hipGetLastError(); st = from_hip(e); break; }
         if (stats) {
             stats->sample_kernel_ms += ev_sample.ms();
@@ -397,6 +419,28 @@ mih_status engine_batch(mih::Engine &eng, const uint64_t *queries, uint32_t nq,
         MIH_TRY(eng.step(completed));
         if (++guard > (1ull << 24)) return MIH_ERR_DEVICE;   // cannot happen: every round advances
     }
+    return MIH_OK;
+}
+
+void copy_stats(const mih::EngineStats &es, clk::time_point t0, mih_query_stats *stats)
+{
+    stats->probes = es.probes;
+    stats->candidates = es.candidates;
+    stats->appended = es.appended;
+    stats->steps = es.steps;
+    stats->rounds = es.rounds;
+    stats->reruns = es.reruns;
+    stats->search_kernel_ms = es.search_kernel_ms;
+    stats->search_launches = es.search_launches;
+    stats->elapsed_ms = ms_since(t0);
+}
+
+// Per-query radius as a host vector.
+mih_status read_radius(uint32_t nq, uint32_t r, const uint32_t *r_per_query, hipStream_t s,
+                       std::vector<uint32_t> &out)
+{
+    out.assign(nq, r);
+    if (r_per_query && nq) MIH_TRY(download(out.data(), r_per_query, sizeof(uint32_t) * nq, s));
     return MIH_OK;
 }
 
@@ -646,15 +690,7 @@ mih_status mih_knn_ex(const mih_index *cidx, const uint64_t *queries, uint32_t n
     if (stats) {
         mih::EngineStats es;
         MIH_TRY(eng.read_stats(es));
-        stats->probes = es.probes;
-        stats->candidates = es.candidates;
-        stats->appended = es.appended;
-        stats->steps = es.steps;
-        stats->rounds = es.rounds;
-        stats->reruns = es.reruns;
-        stats->search_kernel_ms = es.search_kernel_ms;
-        stats->search_launches = es.search_launches;
-        stats->elapsed_ms = ms_since(t0);
+        copy_stats(es, t0, stats);
     }
     return MIH_OK;
 }
@@ -666,6 +702,114 @@ mih_status mih_knn(const mih_index *idx, const uint64_t *queries, uint32_t nq, u
 }
 
 void mih_free(mih_index *idx) { delete idx; }
+
+// ------------------------------------------------------- r-neighbour search
+
+mih_status mih_rnn_ex(const mih_index *cidx, const uint64_t *queries, uint32_t nq, uint32_t r,
+                      const uint32_t *r_per_query, void *stream, mih_rnn_result **out,
+                      mih_query_stats *stats)
+{
+    auto t0 = clk::now();
+    if (!cidx || !out) return MIH_ERR_INVALID;
+    *out = nullptr;
+    mih_index *ix = const_cast<mih_index *>(cidx);
+    if (nq && (!queries || ((uintptr_t)queries & 7) != 0)) return MIH_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(ix->mu);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    std::vector<uint32_t> rv;
+    MIH_TRY_STATUS(read_radius(nq, r, r_per_query, s, rv));
+    std::unique_ptr<mih_rnn_result> res(new (std::nothrow) mih_rnn_result);
+    if (!res) return MIH_ERR_NOMEM;
+    const uint32_t slots = std::min<uint32_t>(std::max<uint32_t>(nq, 1), 1u << 16);
+    const uint64_t pool = (uint64_t)slots * mih::kRnnCapacity;
+    if (!ix->batch_engine || ix->batch_engine->slots() < slots || ix->batch_engine->pool_entries() < pool) {
+        ix->batch_engine.reset();
+        std::unique_ptr<mih::Engine> e(new (std::nothrow) mih::Engine(ix, s));
+        if (!e) return MIH_ERR_NOMEM;
+        hipError_t he = e->init(slots, pool, use_graphs());
+        if (he != hipSuccess) { (void)hipGetLastError(); return from_hip(he); }
+        ix->batch_engine = std::move(e);
+    }
+    mih::Engine &eng = *ix->batch_engine;
+    eng.set_stream(s);
+    MIH_TRY(eng.reset_stats());
+    const uint64_t ticket = eng.submit_rnn(queries, nq, rv.data());
+    std::vector<uint64_t> completed;
+    uint64_t guard = 0;
+    while (!eng.idle()) {
+        hipError_t he = eng.step(completed);
+        if (he != hipSuccess) { (void)hipGetLastError(); ix->batch_engine.reset(); return from_hip(he); }
+        if (++guard > (1ull << 24)) { ix->batch_engine.reset(); return MIH_ERR_DEVICE; }
+    }
+    if (!eng.take_rnn(ticket, res->out)) { ix->batch_engine.reset(); return MIH_ERR_DEVICE; }
+    if (stats) {
+        mih::EngineStats es;
+        MIH_TRY(eng.read_stats(es));
+        copy_stats(es, t0, stats);
+    }
+    *out = res.release();
+    return MIH_OK;
+}
+
+mih_status mih_rnn(const mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t r,
+                   const uint32_t *r_per_query, void *stream, mih_rnn_result **out)
+{
+    return mih_rnn_ex(idx, queries, nq, r, r_per_query, stream, out, nullptr);
+}
+
+mih_status linscan_rnn(const uint64_t *codes, uint64_t n, uint32_t bits, const uint64_t *queries,
+                       uint32_t nq, uint32_t r, const uint32_t *r_per_query, void *stream,
+                       mih_rnn_result **out)
+{
+    if (!out) return MIH_ERR_INVALID;
+    *out = nullptr;
+    if (!bits_ok(bits)) return MIH_ERR_INVALID;
+    if (nq && (!queries || ((uintptr_t)queries & 7) != 0)) return MIH_ERR_INVALID;
+    if (n > 0xFFFFFFFEull || (n && !codes) || ((uintptr_t)codes & 7) != 0) return MIH_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint32_t> rv;
+    MIH_TRY_STATUS(read_radius(nq, r, r_per_query, s, rv));
+    for (uint32_t &v : rv) v = std::min(v, bits);
+    std::unique_ptr<mih_rnn_result> res(new (std::nothrow) mih_rnn_result);
+    if (!res) return MIH_ERR_NOMEM;
+    mih::RnnCollector col(nq);
+    if (n > 0 && nq > 0) {
+        Scratch dtau;
+        MIH_TRY(dtau.ensure(4ull * nq));
+        mih_status st = from_hip(upload(dtau.ptr, rv.data(), 4ull * nq, s));
+        BatchSpec b;
+        b.queries = queries;
+        b.nq = nq;
+        b.k.assign(nq, mih::kRnnK);
+        b.row_off.resize(nq);
+        for (uint32_t i = 0; i < nq; ++i) b.row_off[i] = i;
+        b.cap.assign(nq, mih::kRnnCapacity);
+        b.tau0 = (const uint32_t *)dtau.ptr;
+        b.rnn = &col;
+        if (st == MIH_OK) st = linscan_batch(codes, n, bits, b, nullptr, nullptr, s, 0, nullptr);
+        (void)hipStreamSynchronize(s);
+        dtau.release();
+        MIH_TRY_STATUS(st);
+    }
+    MIH_TRY(col.finish(bits, s, res->out));
+    *out = res.release();
+    return MIH_OK;
+}
+
+mih_status mih_rnn_result_view(const mih_rnn_result *res, mih_rnn_view *view)
+{
+    if (!res || !view) return MIH_ERR_INVALID;
+    view->total = res->out.total;
+    view->nq = res->out.nq;
+    view->pad = 0;
+    view->offsets = res->out.offsets;
+    view->ids = res->out.ids;
+    view->dists = res->out.dists;
+    return MIH_OK;
+}
+
+void mih_rnn_result_free(mih_rnn_result *res) { delete res; }
 
 mih_status mih_index_get_info(const mih_index *idx, mih_index_info *info)
 {

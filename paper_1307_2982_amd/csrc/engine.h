@@ -11,6 +11,7 @@
 
 #include "mih_common.h"
 #include "mih_query.h"
+#include "rnn.h"
 
 namespace mih {
 
@@ -31,6 +32,13 @@ private:
 
 // Candidate-buffer capacity given to a query with this k (entries).
 inline uint32_t search_capacity(uint32_t k) { return k == 0 ? 0u : (k * 8u > 2048u ? k * 8u : 2048u); }
+
+// The k of an r-neighbour query: no count ever reaches it, so its bound
+// stays at the radius.
+constexpr uint32_t kRnnK = 0xFFFFFFFFu;
+// First candidate-buffer capacity of an r-neighbour query (entries); a query
+// with more hits is re-run with the exact count.
+constexpr uint32_t kRnnCapacity = 1024;
 
 class Engine;
 
@@ -84,6 +92,11 @@ public:
     // row_off[i] in out_ids / out_dists (device).  Returns its ticket.
     uint64_t submit(const uint64_t *queries, uint32_t nq, const uint32_t *k,
                     const uint64_t *row_off, uint32_t *out_ids, uint32_t *out_dists);
+    // A request of nq r-neighbour queries with per-query radius (host).  Its
+    // results are taken with take_rnn() once the ticket has completed.
+    uint64_t submit_rnn(const uint64_t *queries, uint32_t nq, const uint32_t *radius);
+    // Hands over the output buffers of a completed r-neighbour request.
+    bool take_rnn(uint64_t ticket, RnnOut &out);
     // One round; tickets of requests completed in it are appended.
     hipError_t step(std::vector<uint64_t> &completed);
     bool idle() const { return in_flight_ == 0 && pending_.empty() && reruns_.empty(); }
@@ -103,6 +116,8 @@ private:
         std::vector<uint64_t> row_off;
         uint32_t *out_ids, *out_dists;
         uint32_t next = 0, done = 0;
+        std::vector<uint32_t> radius;            // r-neighbour requests only
+        std::unique_ptr<RnnCollector> rnn;       // non-null for r-neighbour requests
     };
     struct SlotInfo {
         uint64_t ticket = 0;
@@ -115,6 +130,8 @@ private:
 
     hipError_t admit();
     hipError_t run_round();
+    hipError_t collect_rnn(const std::vector<uint32_t> &slots);
+    hipError_t complete(uint64_t ticket, Req &r, std::vector<uint64_t> &completed);
     hipError_t capture_graph();
     void fill_args(MihArgs &A) const;
 
@@ -129,6 +146,7 @@ private:
     uint32_t *t_ = nullptr, *active_ = nullptr, *active_tmp_ = nullptr, *next_t_ = nullptr;
     uint32_t *new_slots_ = nullptr, *done_list_ = nullptr, *ovf_list_ = nullptr;
     uint32_t *bound_tau_ = nullptr, *bound_cap_ = nullptr;
+    uint32_t *tmp_list_ = nullptr, *tmp_cnt_ = nullptr;
     uint64_t *out_ids_ = nullptr, *out_dists_ = nullptr;
     Group *groups_ = nullptr;
     Control *ctrl_ = nullptr;
@@ -146,6 +164,7 @@ private:
     std::unordered_map<uint64_t, Req> reqs_;
     std::deque<uint64_t> pending_;
     std::deque<Rerun> reruns_;
+    std::unordered_map<uint64_t, RnnOut> rnn_out_;   // finished r-neighbour requests
     uint64_t next_ticket_ = 1;
     uint32_t in_flight_ = 0;       // admitted queries not yet finished
     bool ctrl_has_active_ = false;

@@ -103,6 +103,7 @@ Engine::~Engine()
     if (ctrl_host_) (void)hipHostFree(ctrl_host_);
     if (pool_mem_) (void)hipFree(pool_mem_);
     if (dev_) (void)hipFree(dev_);
+    for (auto &kv : rnn_out_) free_rnn_out(kv.second);
 }
 
 hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
@@ -119,7 +120,8 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
                    o_nt = take(4ull * S_), o_new = take(4ull * S_), o_done = take(4ull * S_),
                    o_ovf = take(4ull * S_), o_btau = take(4ull * S_), o_bcap = take(4ull * S_),
                    o_grp = take(sizeof(Group) * (ix_->t_all + 1)), o_ctrl = take(sizeof(Control)),
-                   o_work = take(8), o_stats = take(8 * 4), o_adm = take(sizeof(AdmitRec) * S_);
+                   o_work = take(8), o_stats = take(8 * 4), o_adm = take(sizeof(AdmitRec) * S_),
+                   o_tl = take(4ull * S_), o_tc = take(4ull * S_);
     hipError_t e = hipMalloc(&dev_, used);
     if (e != hipSuccess) { dev_ = nullptr; return e; }
     char *b = (char *)dev_;
@@ -148,6 +150,8 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
     work_ = (unsigned long long *)(b + o_work);
     stats_ = (unsigned long long *)(b + o_stats);
     admit_dev_ = (AdmitRec *)(b + o_adm);
+    tmp_list_ = (uint32_t *)(b + o_tl);
+    tmp_cnt_ = (uint32_t *)(b + o_tc);
 
     const uint64_t pe = pool_entries ? pool_entries : 1;
     e = hipMalloc((void **)&pool_mem_, pe * 8);
@@ -215,6 +219,31 @@ uint64_t Engine::submit(const uint64_t *queries, uint32_t nq, const uint32_t *k,
     return ticket;
 }
 
+uint64_t Engine::submit_rnn(const uint64_t *queries, uint32_t nq, const uint32_t *radius)
+{
+    const uint64_t ticket = next_ticket_++;
+    Req r;
+    r.queries = queries;
+    r.nq = nq;
+    r.k.assign(nq, kRnnK);
+    r.row_off.assign(nq, 0);
+    r.out_ids = r.out_dists = nullptr;
+    r.radius.assign(radius, radius + nq);
+    r.rnn.reset(new RnnCollector(nq));
+    reqs_.emplace(ticket, std::move(r));
+    pending_.push_back(ticket);
+    return ticket;
+}
+
+bool Engine::take_rnn(uint64_t ticket, RnnOut &out)
+{
+    auto it = rnn_out_.find(ticket);
+    if (it == rnn_out_.end()) return false;
+    out = it->second;
+    rnn_out_.erase(it);
+    return true;
+}
+
 uint32_t Engine::pending_queries() const
 {
     uint32_t p = 0;
@@ -258,8 +287,8 @@ hipError_t Engine::admit()
         a.tau0 = rr.tau0;
         a.buf_off = off;
         a.query = (uint64_t)(uintptr_t)(qb_.queries + (uint64_t)rr.slot * W);
-        a.out_ids = (uint64_t)(uintptr_t)(r.out_ids + r.row_off[si.query]);
-        a.out_dists = (uint64_t)(uintptr_t)(r.out_dists + r.row_off[si.query]);
+        a.out_ids = r.rnn ? 0 : (uint64_t)(uintptr_t)(r.out_ids + r.row_off[si.query]);
+        a.out_dists = r.rnn ? 0 : (uint64_t)(uintptr_t)(r.out_dists + r.row_off[si.query]);
         recs.push_back(a);
         reruns_.pop_front();
     }
@@ -276,7 +305,7 @@ hipError_t Engine::admit()
                 continue;
             }
             uint64_t off;
-            const uint32_t cap = search_capacity(k);
+            const uint32_t cap = r.rnn ? kRnnCapacity : search_capacity(k);
             if (free_slots_.empty() || !pool_.alloc(cap, off)) { stalled = true; break; }
             const uint32_t slot = free_slots_.back();
             free_slots_.pop_back();
@@ -285,11 +314,12 @@ hipError_t Engine::admit()
             a.slot = slot;
             a.k = k;
             a.cap = cap;
-            a.tau0 = ix_->bits;
+            // an r-neighbour query starts (and stays) at its radius
+            a.tau0 = r.rnn ? std::min(r.radius[i], ix_->bits) : ix_->bits;
             a.buf_off = off;
             a.query = (uint64_t)(uintptr_t)(r.queries + (uint64_t)i * W);
-            a.out_ids = (uint64_t)(uintptr_t)(r.out_ids + r.row_off[i]);
-            a.out_dists = (uint64_t)(uintptr_t)(r.out_dists + r.row_off[i]);
+            a.out_ids = r.rnn ? 0 : (uint64_t)(uintptr_t)(r.out_ids + r.row_off[i]);
+            a.out_dists = r.rnn ? 0 : (uint64_t)(uintptr_t)(r.out_dists + r.row_off[i]);
             recs.push_back(a);
             r.next++;
             in_flight_++;
@@ -381,10 +411,11 @@ hipError_t Engine::step(std::vector<uint64_t> &completed)
 {
     hipError_t e = admit();
     if (e != hipSuccess) return e;
-    // requests that needed no search (every k = 0) are complete already
+    // requests that needed no search (every k = 0, or no queries) are complete already
     for (auto it = reqs_.begin(); it != reqs_.end();) {
         if (it->second.next == it->second.nq && it->second.done == it->second.nq) {
-            completed.push_back(it->first);
+            const uint64_t ticket = it->first;
+            if ((e = complete(ticket, it->second, completed)) != hipSuccess) return e;
             it = reqs_.erase(it);
         } else {
             ++it;
@@ -397,7 +428,23 @@ hipError_t Engine::step(std::vector<uint64_t> &completed)
     if (n_done) {
         if ((e = sync_copy(done.data(), done_list_, 4ull * n_done, hipMemcpyDeviceToHost, s_)) != hipSuccess)
             return e;
-        if ((e = finalize_list(qb_, done_list_, n_done, out_ids_, out_dists_, s_)) != hipSuccess) return e;
+        std::vector<uint32_t> knn, rnn;
+        for (uint32_t q : done) {
+            auto it = reqs_.find(slot_info_[q].ticket);
+            (it != reqs_.end() && it->second.rnn ? rnn : knn).push_back(q);
+        }
+        if (!rnn.empty() && (e = collect_rnn(rnn)) != hipSuccess) return e;
+        if (!knn.empty()) {
+            const uint32_t *list = done_list_;
+            if (knn.size() != n_done) {
+                if ((e = sync_copy(tmp_list_, knn.data(), 4ull * knn.size(), hipMemcpyHostToDevice, s_)) !=
+                    hipSuccess)
+                    return e;
+                list = tmp_list_;
+            }
+            if ((e = finalize_list(qb_, list, (uint32_t)knn.size(), out_ids_, out_dists_, s_)) != hipSuccess)
+                return e;
+        }
     }
     if (n_ovf) {
         if ((e = sync_copy(ovf.data(), ovf_list_, 4ull * n_ovf, hipMemcpyDeviceToHost, s_)) != hipSuccess)
@@ -428,10 +475,51 @@ hipError_t Engine::step(std::vector<uint64_t> &completed)
         Req &r = it->second;
         r.done++;
         if (r.done == r.nq && r.next == r.nq) {
-            completed.push_back(it->first);
+            if ((e = complete(it->first, r, completed)) != hipSuccess) return e;
             reqs_.erase(it);
         }
     }
+    return hipSuccess;
+}
+
+// Moves the hits of finished r-neighbour queries out of their candidate
+// buffers into their requests' collectors.
+hipError_t Engine::collect_rnn(const std::vector<uint32_t> &slots)
+{
+    const uint32_t n = (uint32_t)slots.size();
+    hipError_t e = sync_copy(tmp_list_, slots.data(), 4ull * n, hipMemcpyHostToDevice, s_);
+    if (e == hipSuccess) e = gather_counts(qb_.count, tmp_list_, n, tmp_cnt_, s_);
+    std::vector<uint32_t> cnt(n);
+    if (e == hipSuccess) e = sync_copy(cnt.data(), tmp_cnt_, 4ull * n, hipMemcpyDeviceToHost, s_);
+    if (e != hipSuccess) return e;
+    // one add per request
+    std::unordered_map<uint64_t, std::vector<uint32_t>> by_req;
+    for (uint32_t i = 0; i < n; ++i) by_req[slot_info_[slots[i]].ticket].push_back(i);
+    for (auto &kv : by_req) {
+        Req &r = reqs_.at(kv.first);
+        std::vector<uint32_t> query, count;
+        std::vector<uint64_t> src;
+        for (uint32_t i : kv.second) {
+            const SlotInfo &si = slot_info_[slots[i]];
+            query.push_back(si.query);
+            src.push_back(si.buf_off);
+            count.push_back(cnt[i]);
+        }
+        if ((e = r.rnn->add(qb_.buf, query, src, count, s_)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t Engine::complete(uint64_t ticket, Req &r, std::vector<uint64_t> &completed)
+{
+    if (r.rnn) {
+        RnnOut out;
+        hipError_t e = r.rnn->finish(ix_->bits, s_, out);
+        if (e != hipSuccess) return e;
+        rnn_out_[ticket] = out;
+        r.rnn.reset();
+    }
+    completed.push_back(ticket);
     return hipSuccess;
 }
 

@@ -93,18 +93,7 @@ __device__ void finalize_one(const QueryBatch &qb, uint32_t q, uint32_t *oid, ui
     while (P < kk) P <<= 1;
     for (uint32_t i = kk + tid; i < P; i += MIH_BLOCK) sel[i] = ~0ull;
     __syncthreads();
-    for (uint32_t size = 2; size <= P; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t i = tid; i < P / 2; i += MIH_BLOCK) {
-                uint32_t lo = 2 * stride * (i / stride) + (i % stride);
-                uint32_t hi = lo + stride;
-                bool up = (lo & size) == 0;
-                uint64_t x = sel[lo], y = sel[hi];
-                if ((x > y) == up) { sel[lo] = y; sel[hi] = x; }
-            }
-            __syncthreads();
-        }
-    }
+    block_bitonic_sort(sel, P);
     for (uint32_t r = tid; r < k; r += MIH_BLOCK) {
         if (r < kk) {
             oid[r] = (uint32_t)sel[r];

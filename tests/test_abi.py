@@ -50,3 +50,9 @@ def test_argument_errors_need_no_device():
     assert lib.mih_build(None, 0, 64, 2, None, None, None) == 1                   # out NULL
     assert lib.linscan_knn(None, 0, 64, None, 1, 5, None, None, None, None) == 1  # queries NULL
     assert lib.mih_knn(None, None, 0, 1, None, None, None, None) == 1             # index NULL
+    assert lib.mih_rnn(None, None, 0, 3, None, None, ctypes.byref(h)) == 1        # index NULL
+    assert lib.linscan_rnn(None, 0, 96, None, 0, 3, None, None, ctypes.byref(h)) == 1   # bad bits
+    assert lib.linscan_rnn(None, 0, 64, None, 2, 3, None, None, ctypes.byref(h)) == 1   # queries NULL
+    assert lib.linscan_rnn(None, 0, 64, None, 0, 3, None, None, None) == 1        # out NULL
+    assert lib.mih_rnn_result_view(None, None) == 1
+    lib.mih_rnn_result_free(None)                                                 # ignored
