@@ -54,8 +54,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch tuning")
     ap.add_argument("--autotune-sample", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
-    ap.add_argument("--serve-requests", type=int, default=300)
-    ap.add_argument("--serve-warmup", type=int, default=30)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-loads", default="0.5,0.9",
                     help="fractions of the closed-loop capacity to replay the stream at")
     ap.add_argument("--serve-slots", type=int, default=16384)
@@ -63,6 +63,9 @@ def parse():
                     help="also time the search over a grid of launch tunings")
     ap.add_argument("--m-sweep", default="",
                     help="comma-separated extra m values to build and time (e.g. 3,4)")
+    ap.add_argument("--rnn", type=int, default=None,
+                    help="radius of the r-neighbour leg (default 10 per 64 bits of code)")
+    ap.add_argument("--no-rnn", action="store_true", help="skip the r-neighbour leg")
     ap.add_argument("--copy-calib", type=float, default=0.0,
                     help="also run one plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
@@ -401,6 +404,36 @@ def main():
         log(f"linscan: {lin_ms:.1f} ms/step -> {lin_qps:,.0f} queries/s; parity with MIH: "
             f"{parity_mih_vs_linscan}; kernel {scan_ms:.1f} ms = {achieved_ops:.2f} Tops/s")
 
+    # ---------------- r-neighbour search: MIH vs linear scan, same queries
+    rnn = None
+    if not args.no_rnn:
+        R = args.rnn if args.rnn is not None else 10 * W
+        idx.rnn(dq, R)
+        torch.cuda.synchronize()
+        rms = []
+        for _ in range(max(1, args.steps)):
+            t = time.perf_counter()
+            ro, ri, rd, rst = idx.rnn(dq, R, stats=True)
+            torch.cuda.synchronize()
+            rms.append((time.perf_counter() - t) * 1e3)
+        r_ms = float(np.mean(rms))
+        rnn = {"r": R, "mih_queries_per_s": round(nq / (r_ms / 1e3), 1), "mih_ms": round(r_ms, 2),
+               "results_per_query": int(ro[-1]) / nq, "probes_per_query": rst["probes"] / nq,
+               "candidates_per_query": rst["candidates"] / nq, "reruns": rst["reruns"]}
+        if not args.no_linscan:
+            t = time.perf_counter()
+            lo_, li_, ld_ = mih.linscan_rnn(dc, dq, R)
+            torch.cuda.synchronize()
+            l_ms = (time.perf_counter() - t) * 1e3
+            rnn.update({"linscan_queries_per_s": round(nq / (l_ms / 1e3), 1), "linscan_ms": round(l_ms, 2),
+                        "speedup_mih_over_linscan": round(l_ms / r_ms, 2),
+                        "parity_with_linscan": bool(torch.equal(ro, lo_) and torch.equal(ri, li_)
+                                                    and torch.equal(rd, ld_))})
+            del lo_, li_, ld_
+        log(f"r-neighbours r={R}: MIH {r_ms:.1f} ms ({rnn['mih_queries_per_s']:,.0f} q/s), "
+            f"{rnn['results_per_query']:.1f} results/query; linscan {rnn.get('linscan_ms')} ms, "
+            f"same={rnn.get('parity_with_linscan')}")
+
     # ---------------- CPU oracle: bounded sample, also a full-size parity check
     cpu = None
     parity_oracle = None
@@ -436,6 +469,18 @@ def main():
                          f"same k; {spent:.1f} s wall on {used} host threads"}
         parity_oracle = {"queries_checked": done, "bit_exact": ok}
         log(f"oracle: {done} queries in {spent:.1f}s on {used} threads; MIH == oracle: {ok}")
+        if rnn is not None:
+            # two queries' r-neighbour lists against the oracle's definition
+            roff = ro.cpu().numpy()
+            rid = ri.cpu().numpy().view(np.uint32)
+            rdd = rd.cpu().numpy().view(np.uint32)
+            rok = True
+            for q in order[:2]:
+                oi, od = oracle.rnn(codes, queries[q], rnn["r"])
+                rok &= bool(np.array_equal(oi, rid[roff[q]:roff[q + 1]]) and
+                            np.array_equal(od, rdd[roff[q]:roff[q + 1]]))
+            rnn["parity_with_oracle_2_queries"] = rok
+            log(f"r-neighbours of 2 queries == oracle: {rok}")
 
     out = {
         "metric": METRIC,
@@ -465,6 +510,7 @@ def main():
         "roofline": roofline,
         "serving": serving,
         "linscan": lin,
+        "rnn": rnn,
         "cpu_baseline": cpu,
         "parity": {"mih_vs_oracle_sample": parity_oracle,
                    "mih_vs_linscan_all": lin["parity_with_mih"] if lin else None},

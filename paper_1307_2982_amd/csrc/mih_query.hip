@@ -288,14 +288,18 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
         cum += h[d];
         if (cum >= k) { D = d; break; }
     }
-    if (D != 0xFFFFFFFFu && D < A.qb.tau[q]) A.qb.tau[q] = D;
+    // the bound: the k-th distance found so far, or the query's own radius
+    // (r-neighbour queries, exact re-runs) when that is smaller
+    uint32_t tau = A.qb.tau[q];
+    if (D < tau) { A.qb.tau[q] = D; tau = D; }
     uint32_t t = A.t[q];
     uint32_t out = 0xFFFFFFFFu;
-    if (!(D <= t || t >= A.t_all)) {
+    // after step t every code within distance t has been found (Prop. 2)
+    if (!(tau <= t || t >= A.t_all)) {
         for (uint32_t tn = t + 1;; ++tn) {
             const uint32_t rp = tn / A.m;
             if (binom_calc(A.tables[tn - rp * A.m].len, rp) > 0) { out = tn; break; }
-            if (D <= tn || tn >= A.t_all) break;
+            if (tau <= tn || tn >= A.t_all) break;
         }
     }
     A.next_t[i] = out;

@@ -6,6 +6,7 @@ import pytest
 
 import datagen
 import oracle
+from oracle import formulas
 from gpu_util import as_u32, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -60,9 +61,14 @@ def test_mih_rnn_uniform_radii(mih, tmode, cmode):
     queries[3] = codes[17]          # an exact match (r = 0 finds it)
     idx = mih.build(to_dev(codes), 3, table_mode=tmode, codes_mode=cmode)
     dq = to_dev(queries)
+    lens, _ = formulas.partition(64, 3)
     for r in [0, 3, 9, 14, 17]:
-        got = idx.rnn(dq, r)
-        assert_rnn_same(got, oracle_rnn_all(codes, queries, [r] * nq), f"{tmode}/{cmode} r={r}")
+        off, ids, dists, st = idx.rnn(dq, r, stats=True)
+        assert_rnn_same((off, ids, dists), oracle_rnn_all(codes, queries, [r] * nq),
+                        f"{tmode}/{cmode} r={r}")
+        # steps 0..r and nothing more: C(s_a, r') buckets per step (Eq. 1)
+        assert st["steps"] == nq * (r + 1)
+        assert st["probes"] == nq * sum(formulas.shell(lens[t % 3], t // 3) for t in range(r + 1))
     idx.close()
 
 
