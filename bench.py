@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--rnn", type=int, default=None,
                     help="radius of the r-neighbour leg (default 10 per 64 bits of code)")
     ap.add_argument("--no-rnn", action="store_true", help="skip the r-neighbour leg")
+    ap.add_argument("--choose-m", action="store_true",
+                    help="also pick m by timing candidates on 1000 database rows (Section 6)")
     ap.add_argument("--copy-calib", type=float, default=0.0,
                     help="also run one plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
@@ -362,6 +364,19 @@ def main():
             del ix2
             torch.cuda.synchronize()
 
+    chosen_m = None
+    if args.choose_m:
+        kk = int(ks[-1]) if mixed_k else int(ks[0])
+        t = time.time()
+        best_m, trials = mih.choose_m(dc, kk, validation=1000, seed=9, table_mode=args.table_mode,
+                                      codes_mode=args.codes_mode)
+        chosen_m = {"k": kk, "validation": "1000 database rows (seeded permutation)", "best_m": best_m,
+                    "model_radius": mih.model_radius(n, bits, kk), "heuristic_b_over_log2n":
+                    round(bits / np.log2(n), 3), "trials": trials}
+        log(f"choose m (k={kk}): best m={best_m} in {time.time() - t:.1f}s; " +
+            ", ".join(f"m={t_['m']}: {t_['search_ms']:.1f} ms (model {t_['model_cost']:.3g})" for t_ in trials))
+        torch.cuda.synchronize()
+
     # ---------------- serving loop (continuous batching)
     serving = None
     if not args.no_serve:
@@ -519,6 +534,7 @@ def main():
         "autotuned": tuned is not None,
         "tuning_sweep": sweep,
         "m_sweep": m_sweep,
+        "choose_m": chosen_m,
         "mih_stats": {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in stats[-1].items()},
     }
     print(json.dumps(out), flush=True)

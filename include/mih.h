@@ -253,7 +253,9 @@ typedef struct mih_tuning {
                                   occupancy map before reading the offsets   */
 } mih_tuning;
 
-/* Current tuning of an index (defaults after mih_build: 4, 8192, 0). */
+/* Current tuning of an index (defaults after mih_build: 4, 8192, 0, and
+ * the occupancy filter on for DIRECT tables of substrings of 26 bits or
+ * more). */
 mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
 
 /* Replace the tuning; MIH_ERR_INVALID (index unchanged) if a field is out of
@@ -267,6 +269,52 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning);
  * sample only has to look like the real queries.  Arguments as mih_knn. */
 mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
                         const uint32_t *k_per_query, void *stream, mih_tuning *chosen);
+
+/* ---- Choosing the number of substrings (Section 3.1; Section 6) -------
+ *
+ * Cost model of Eq. 6 for uniform codes, in units of one lookup: for each
+ * table of s bits, (1 + n / 2^s) times the buckets within substring radius
+ * floor(s r / bits).  Tables of unequal length (bits not divisible by m)
+ * contribute their own terms; with s = bits / m for all tables this is
+ * Eq. 6.  Returns 0 for m = 0 or m > bits. */
+double mih_model_cost(uint64_t n, uint32_t bits, uint32_t m, uint32_t r);
+
+/* Model radius of a kNN query over n uniform codes: the smallest r whose
+ * expected count of codes within distance r, n L(bits, r) / 2^bits (Eq. 1),
+ * is at least k; 0 for k = 0, bits when k >= n. */
+uint32_t mih_model_radius(uint64_t n, uint32_t bits, uint32_t k);
+
+#define MIH_M_TRIALS_MAX 16u
+
+/* One candidate m timed by mih_choose_m. */
+typedef struct mih_m_trial {
+    uint32_t m;
+    mih_status status;      /* MIH_OK, or why this m could not be timed     */
+    double model_cost;      /* mih_model_cost at mih_model_radius(n, bits, k) */
+    double search_ms;       /* wall time of mih_knn over the validation queries */
+    double build_ms;        /* mih_build of this m                           */
+    uint64_t device_bytes;  /* index memory of this m                        */
+} mih_m_trial;
+
+/* Selects m by timing (Section 6, "Number of Substrings"): for each
+ * candidate m an index is built over the codes, mih_knn is run once to warm
+ * up and once timed over the validation queries, and the index is freed.
+ *   host candidates  [ncand] values of m, or NULL with ncand = 0 for the
+ *                    default set: the integers nearest bits / log2 n (one
+ *                    below, nearest, one above) and the minimiser of
+ *                    mih_model_cost, each with ceil(bits/m) <= 32
+ *   opts             build options for every candidate (NULL = defaults)
+ *   host best_m      the candidate with the smallest search time
+ *   host trials      [MIH_M_TRIALS_MAX] filled for each candidate, or NULL
+ *   host ntrials     number of candidates tried
+ * Codes and queries as in mih_build and mih_knn; one k for all queries.
+ * Errors: MIH_ERR_INVALID for n < 2, nq = 0, k = 0 or k > MIH_K_MAX, an
+ * invalid candidate or more than MIH_M_TRIALS_MAX of them; when no
+ * candidate could be built and timed, the status of the last failure. */
+mih_status mih_choose_m(const uint64_t *codes, uint64_t n, uint32_t bits, const uint64_t *queries,
+                        uint32_t nq, uint32_t k, const uint32_t *candidates, uint32_t ncand,
+                        const mih_build_opts *opts, void *stream, uint32_t *best_m,
+                        mih_m_trial *trials, uint32_t *ntrials);
 
 /* ---- Serving: continuous batching over a built index ------------------
  *

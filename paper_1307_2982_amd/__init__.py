@@ -83,6 +83,20 @@ class Tuning(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class MTrial(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_uint32), ("status", ctypes.c_int), ("model_cost", ctypes.c_double),
+                ("search_ms", ctypes.c_double), ("build_ms", ctypes.c_double),
+                ("device_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["status"] = STATUS.get(d["status"], d["status"])
+        return d
+
+
+M_TRIALS_MAX = 16
+
+
 class RnnView(ctypes.Structure):
     _fields_ = [("total", ctypes.c_uint64), ("nq", ctypes.c_uint32), ("pad", ctypes.c_uint32),
                 ("offsets", ctypes.c_void_p), ("ids", ctypes.c_void_p), ("dists", ctypes.c_void_p)]
@@ -90,6 +104,7 @@ class RnnView(ctypes.Structure):
 
 EXPORTED = ["mih_build", "mih_knn", "mih_knn_ex", "linscan_knn", "linscan_knn_ex", "mih_free",
             "mih_rnn", "mih_rnn_ex", "linscan_rnn", "mih_rnn_result_view", "mih_rnn_result_free",
+            "mih_model_cost", "mih_model_radius", "mih_choose_m",
             "mih_status_str", "mih_index_get_info", "mih_index_table", "mih_get_tuning",
             "mih_set_tuning", "mih_autotune", "mih_server_create", "mih_server_submit", "mih_server_step",
             "mih_server_poll", "mih_server_get_stats", "mih_server_destroy"]
@@ -133,6 +148,13 @@ def load():
     L.mih_rnn_result_view.restype = i32
     L.mih_rnn_result_free.argtypes = [vp]
     L.mih_rnn_result_free.restype = None
+    L.mih_model_cost.argtypes = [u64, u32, u32, u32]
+    L.mih_model_cost.restype = ctypes.c_double
+    L.mih_model_radius.argtypes = [u64, u32, u32]
+    L.mih_model_radius.restype = u32
+    L.mih_choose_m.argtypes = [vp, u64, u32, vp, u32, u32, vp, u32, ctypes.POINTER(BuildOpts), vp,
+                               ctypes.POINTER(u32), ctypes.POINTER(MTrial), ctypes.POINTER(u32)]
+    L.mih_choose_m.restype = i32
     L.mih_status_str.argtypes = [i32]
     L.mih_status_str.restype = ctypes.c_char_p
     L.mih_index_get_info.argtypes = [vp, ctypes.POINTER(IndexInfo)]
@@ -324,6 +346,45 @@ def build(codes: torch.Tensor, m: int, table_mode: str = "auto", codes_mode: str
                           _stream(), ctypes.byref(h))
     _check(rc, "mih_build")
     return Index(h, codes)
+
+
+def model_cost(n: int, bits: int, m: int, r: int) -> float:
+    """Eq. 6 cost (in lookups) of searching radius r with m tables over n uniform codes."""
+    return load().mih_model_cost(n, bits, m, r)
+
+
+def model_radius(n: int, bits: int, k: int) -> int:
+    """Smallest r with at least k expected uniform codes within distance r."""
+    return load().mih_model_radius(n, bits, k)
+
+
+def choose_m(codes: torch.Tensor, k: int, queries: torch.Tensor | None = None,
+             validation: int = 1000, candidates=None, table_mode: str = "auto",
+             codes_mode: str = "auto", seed: int = 0):
+    """Pick m by building and timing each candidate (Section 6).  Without
+    `queries`, `validation` database rows chosen with a seeded permutation
+    serve as the validation queries.  Returns (best m, list of trial dicts)."""
+    codes = _codes_arg(codes, "codes")
+    n, W = codes.shape
+    if queries is None:
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        rows = torch.randperm(n, generator=g)[:min(validation, n)].to(codes.device)
+        queries = codes.index_select(0, rows).contiguous()
+    queries = _codes_arg(queries, "queries")
+    cand = None
+    nc = 0
+    if candidates is not None:
+        nc = len(candidates)
+        cand = (ctypes.c_uint32 * max(nc, 1))(*candidates)
+    opts = BuildOpts(TABLE_MODES[table_mode], CODES_MODES[codes_mode], 0)
+    best = ctypes.c_uint32()
+    ntr = ctypes.c_uint32()
+    trials = (MTrial * M_TRIALS_MAX)()
+    rc = load().mih_choose_m(codes.data_ptr() if n else None, n, 64 * W, queries.data_ptr(),
+                             queries.shape[0], k, cand, nc, ctypes.byref(opts), _stream(),
+                             ctypes.byref(best), trials, ctypes.byref(ntr))
+    _check(rc, "mih_choose_m")
+    return best.value, [trials[i].as_dict() for i in range(ntr.value)]
 
 
 def _r_arg(r, nq: int, device):
