@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--nq", type=int, default=None, help="override the number of queries")
     ap.add_argument("--k", type=int, default=None, help="override k (single value)")
     ap.add_argument("--m", type=int, default=None, help="override the number of substrings")
-    ap.add_argument("--table-mode", default="auto", choices=["auto", "direct", "sorted"])
+    ap.add_argument("--table-mode", default="auto", choices=["auto", "direct", "sorted", "grouped"])
     ap.add_argument("--codes-mode", default="auto", choices=["auto", "inline", "indirect"])
     ap.add_argument("--linscan-steps", type=int, default=None)
     ap.add_argument("--no-linscan", action="store_true")
@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--no-rnn", action="store_true", help="skip the r-neighbour leg")
     ap.add_argument("--choose-m", action="store_true",
                     help="also pick m by timing candidates on 1000 database rows (Section 6)")
+    ap.add_argument("--gather-calib", type=float, default=0.0,
+                    help="also time 2^27 random 4-byte reads from an array of this many GiB "
+                         "(the device's random-line rate, a ceiling for the search kernel)")
     ap.add_argument("--copy-calib", type=float, default=0.0,
                     help="also run one plain device copy of this many GiB (counter calibration)")
     return ap.parse_args()
@@ -264,6 +267,32 @@ def main():
         log(f"copy calibration: {words * 8} bytes read and written")
         del a, b
 
+    gather = None
+    if args.gather_calib > 0:
+        # independent random reads: every one touches its own line, as the
+        # probes and candidate reads of the search kernel do
+        words = int(args.gather_calib * 2**30) // 4
+        arr = torch.zeros(words, dtype=torch.int32, device="cuda")
+        g = torch.Generator(device="cuda").manual_seed(11)
+        nread = 1 << 27
+        pos = torch.randint(0, words, (nread,), device="cuda", generator=g)
+        torch.take(arr, pos)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            torch.take(arr, pos)
+        e1.record()
+        torch.cuda.synchronize()
+        g_ms = e0.elapsed_time(e1) / 3
+        gather = {"array_GiB": args.gather_calib, "reads": nread, "ms": round(g_ms, 3),
+                  "random_reads_per_s": round(nread / (g_ms / 1e3), 1),
+                  "note": "torch.take over int64 positions: per read 8 B of position and 4 B of "
+                          "output stream sequentially beside the random 4 B read"}
+        log(f"random reads: {nread} in {g_ms:.2f} ms -> {nread / (g_ms / 1e3) / 1e9:.1f} G reads/s")
+        del arr, pos
+        torch.cuda.synchronize()
+
     # ---------------- launch tuning picked on a sample of the queries
     tuned = None
     if not args.no_autotune:
@@ -294,7 +323,7 @@ def main():
         per_cand = 8 * W
     else:
         per_cand = 4 + 8 * W
-    per_probe = 8 if info["table_mode"] == "direct" else 12
+    per_probe = 12 if info["table_mode"] == "sorted" else 8
     alg_bytes = st["probes"] * per_probe + st["candidates"] * per_cand + st["appended"] * 16
     kern_ms = st["search_kernel_ms"]
     launches = max(1, st["search_launches"])
@@ -321,25 +350,31 @@ def main():
     if args.sweep:
         base_t = idx.get_tuning()
         sweep = []
+        grid = []
         for occ in ((0, 1) if info["table_mode"] == "direct" else (0,)):
-          for J in (4, 8, 16):
-            for chunk in (64 * J * 8, 64 * J * 32, 64 * J * 128):
-                for bpc in (0,):
-                    idx.set_tuning(J, chunk, bpc, occ)
-                    idx.knn(dq, k_arg)
-                    torch.cuda.synchronize()
-                    t = time.perf_counter()
-                    si, sd, sst = idx.knn(dq, k_arg, stats=True)
-                    torch.cuda.synchronize()
-                    ms = (time.perf_counter() - t) * 1e3
-                    same = bool(torch.equal(si, ids) and torch.equal(sd, dists))
-                    sweep.append({"probes_per_lane": J, "chunk": chunk, "blocks_per_cu": bpc,
-                                  "occupancy_filter": occ,
-                                  "ms": round(ms, 2), "kernel_ms": round(sst["search_kernel_ms"], 2),
-                                  "same_result": same})
-                    log(f"tuning occ={occ} J={J} chunk={chunk}: {ms:.1f} ms same={same}")
-        idx.set_tuning(base_t["probes_per_lane"], base_t["chunk"], base_t["blocks_per_cu"],
-                       base_t["occupancy_filter"])
+            for J in (4, 8, 16):
+                for chunk in (64 * J * 8, 64 * J * 32, 64 * J * 128):
+                    grid.append(dict(probes_per_lane=J, chunk=chunk, blocks_per_cu=0,
+                                     occupancy_filter=occ, sweep_shift=0, sweep_bits=18))
+        for shift in (3, 6, 9):
+            for sbits in (16, 18, 20):
+                for J in (4, 8):
+                    grid.append(dict(probes_per_lane=J, chunk=64 * J * 32, blocks_per_cu=0,
+                                     occupancy_filter=base_t["occupancy_filter"], sweep_shift=shift,
+                                     sweep_bits=sbits))
+        for tg in grid:
+            idx.set_tuning(**tg)
+            idx.knn(dq, k_arg)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            si, sd, sst = idx.knn(dq, k_arg, stats=True)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3
+            same = bool(torch.equal(si, ids) and torch.equal(sd, dists))
+            sweep.append(dict(tg, ms=round(ms, 2), kernel_ms=round(sst["search_kernel_ms"], 2),
+                              same_result=same))
+            log(f"tuning {tg}: {ms:.1f} ms same={same}")
+        idx.set_tuning(**base_t)
 
     m_sweep = None
     if args.m_sweep:
@@ -535,6 +570,7 @@ def main():
         "tuning_sweep": sweep,
         "m_sweep": m_sweep,
         "choose_m": chosen_m,
+        "random_read_calibration": gather,
         "mih_stats": {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in stats[-1].items()},
     }
     print(json.dumps(out), flush=True)

@@ -55,14 +55,19 @@ typedef enum mih_status {
 #define MIH_SUBSTRING_MAX 32u  /* longest substring (direct tables, Section 6) */
 
 /* Substring tables.  DIRECT: one offset per substring value, 2^s + 1 uint32
- * entries per table (the direct-address tables of Section 6, stored densely);
- * SORTED: the substring values kept sorted beside the ids, found through a
- * prefix directory and a binary search.  AUTO: DIRECT when it fits the
- * memory budget, else SORTED. */
+ * entries per table (the direct-address tables of Section 6, stored densely),
+ * plus one occupancy bit per value; SORTED: the substring values kept sorted
+ * beside the ids, found through a prefix directory and a binary search;
+ * GROUPED: like the 32-bucket groups of Section 6, one 64-bit record per 32
+ * consecutive values (their occupancy bits and the table position of the
+ * group's first code, 2^s / 4 bytes per table), and a bucket is found by
+ * scanning its group's codes, so GROUPED needs INLINE codes.  AUTO: DIRECT
+ * when it fits the memory budget, else SORTED. */
 typedef enum mih_table_mode {
     MIH_TABLE_AUTO = 0,
     MIH_TABLE_DIRECT = 1,
-    MIH_TABLE_SORTED = 2
+    MIH_TABLE_SORTED = 2,
+    MIH_TABLE_GROUPED = 3
 } mih_table_mode;
 
 /* Where candidate codes are read during verification.  INLINE: each table
@@ -86,7 +91,7 @@ typedef struct mih_index mih_index;   /* opaque, owned by the library */
 typedef struct mih_index_info {
     uint64_t n;
     uint32_t bits, m;
-    uint32_t table_mode;          /* MIH_TABLE_DIRECT or MIH_TABLE_SORTED  */
+    uint32_t table_mode;          /* MIH_TABLE_DIRECT, _SORTED or _GROUPED  */
     uint32_t codes_mode;          /* MIH_CODES_INLINE or MIH_CODES_INDIRECT */
     uint32_t sub_len[MIH_M_MAX];  /* substring lengths s_j                  */
     uint32_t sub_start[MIH_M_MAX];/* first bit of substring j               */
@@ -107,6 +112,10 @@ typedef struct mih_table_view {
     const uint32_t *occupancy;   /* DIRECT: [max(2^len / 32, 1)] words, bit
                                     v % 32 of word v / 32 = [bucket v is
                                     non-empty]; else NULL                   */
+    const uint64_t *groups;      /* GROUPED: [max(2^len / 32, 1)] records:
+                                    bits 0..31 occupancy of values 32g..32g+31,
+                                    bits 32..63 position of the first code
+                                    with value >= 32g; else NULL            */
 } mih_table_view;
 
 /* Per-call counters of the multi-index search (sums over the queries). */
@@ -251,11 +260,16 @@ typedef struct mih_tuning {
     uint32_t blocks_per_cu;    /* persistent workgroups per CU, 0 = all that fit */
     uint32_t occupancy_filter; /* DIRECT tables: 1 = test a one-bit-per-bucket
                                   occupancy map before reading the offsets   */
+    uint32_t sweep_shift;      /* 0: off.  Else a round's group of queries at
+                                  one step of a table of s >= 20 bits whose
+                                  probes reach 2^s >> sweep_shift is run
+                                  partition by partition of the key space   */
+    uint32_t sweep_bits;       /* key bits per sweep partition, 10..32        */
 } mih_tuning;
 
-/* Current tuning of an index (defaults after mih_build: 4, 8192, 0, and
- * the occupancy filter on for DIRECT tables of substrings of 26 bits or
- * more). */
+/* Current tuning of an index (defaults after mih_build: 4, 8192, 0, the
+ * occupancy filter on for DIRECT tables of substrings of 26 bits or more,
+ * sweep off, 18 sweep bits). */
 mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
 
 /* Replace the tuning; MIH_ERR_INVALID (index unchanged) if a field is out of

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libmih.so")
 
 SENTINEL = 0xFFFFFFFF
 K_MAX = 4096
-TABLE_MODES = {"auto": 0, "direct": 1, "sorted": 2}
+TABLE_MODES = {"auto": 0, "direct": 1, "sorted": 2, "grouped": 3}
 CODES_MODES = {"auto": 0, "inline": 1, "indirect": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error",
           4: "unsupported", 5: "no capacity"}
@@ -51,7 +51,7 @@ class TableView(ctypes.Structure):
     _fields_ = [("offsets", ctypes.c_void_p), ("keys", ctypes.c_void_p), ("dir", ctypes.c_void_p),
                 ("ids", ctypes.c_void_p), ("codes", ctypes.c_void_p), ("len", ctypes.c_uint32),
                 ("start", ctypes.c_uint32), ("dir_bits", ctypes.c_uint32), ("pad", ctypes.c_uint32),
-                ("occupancy", ctypes.c_void_p)]
+                ("occupancy", ctypes.c_void_p), ("groups", ctypes.c_void_p)]
 
 
 class QueryStats(ctypes.Structure):
@@ -77,7 +77,8 @@ class ScanStats(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("probes_per_lane", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
-                ("blocks_per_cu", ctypes.c_uint32), ("occupancy_filter", ctypes.c_uint32)]
+                ("blocks_per_cu", ctypes.c_uint32), ("occupancy_filter", ctypes.c_uint32),
+                ("sweep_shift", ctypes.c_uint32), ("sweep_bits", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -250,7 +251,7 @@ class Index:
         _check(load().mih_index_get_info(self._h, ctypes.byref(inf)), "mih_index_get_info")
         m = inf.m
         return {"n": inf.n, "bits": inf.bits, "m": m,
-                "table_mode": {1: "direct", 2: "sorted"}.get(inf.table_mode, inf.table_mode),
+                "table_mode": {1: "direct", 2: "sorted", 3: "grouped"}.get(inf.table_mode, inf.table_mode),
                 "codes_mode": {1: "inline", 2: "indirect"}.get(inf.codes_mode, inf.codes_mode),
                 "sub_len": list(inf.sub_len[:m]), "sub_start": list(inf.sub_start[:m]),
                 "dir_bits": list(inf.dir_bits[:m]), "device_bytes": inf.device_bytes,
@@ -262,10 +263,14 @@ class Index:
         return t.as_dict()
 
     def set_tuning(self, probes_per_lane: int, chunk: int, blocks_per_cu: int = 0,
-                   occupancy_filter: int | None = None):
-        if occupancy_filter is None:
-            occupancy_filter = self.get_tuning()["occupancy_filter"]
-        t = Tuning(probes_per_lane, chunk, blocks_per_cu, occupancy_filter)
+                   occupancy_filter: int | None = None, sweep_shift: int | None = None,
+                   sweep_bits: int | None = None):
+        """Launch tuning (speed only); fields left as None keep their value."""
+        cur = self.get_tuning()
+        occupancy_filter = cur["occupancy_filter"] if occupancy_filter is None else occupancy_filter
+        sweep_shift = cur["sweep_shift"] if sweep_shift is None else sweep_shift
+        sweep_bits = cur["sweep_bits"] if sweep_bits is None else sweep_bits
+        t = Tuning(probes_per_lane, chunk, blocks_per_cu, occupancy_filter, sweep_shift, sweep_bits)
         _check(load().mih_set_tuning(self._h, ctypes.byref(t)), "mih_set_tuning")
 
     def autotune(self, queries: torch.Tensor, k) -> dict:
@@ -297,6 +302,8 @@ class Index:
             out["codes"] = _copy_device(v.codes, n * W, torch.int64).view(n, W)
         if v.occupancy:
             out["occupancy"] = _copy_device(v.occupancy, max((1 << v.len) // 32, 1), torch.int32)
+        if v.groups:
+            out["groups"] = _copy_device(v.groups, max((1 << v.len) // 32, 1), torch.int64)
         return out
 
     def rnn(self, queries: torch.Tensor, r, stats: bool = False):

@@ -521,7 +521,9 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     if (n > 0xFFFFFFFEull || (n && !codes) || ((uintptr_t)codes & 7) != 0) return MIH_ERR_INVALID;
     mih_build_opts o = {MIH_TABLE_AUTO, MIH_CODES_AUTO, 0};
     if (opts) o = *opts;
-    if (o.table_mode > MIH_TABLE_SORTED || o.codes_mode > MIH_CODES_INDIRECT) return MIH_ERR_INVALID;
+    if (o.table_mode > MIH_TABLE_GROUPED || o.codes_mode > MIH_CODES_INDIRECT) return MIH_ERR_INVALID;
+    // a GROUPED table finds a bucket by scanning the codes in table order
+    if (o.table_mode == MIH_TABLE_GROUPED && o.codes_mode == MIH_CODES_INDIRECT) return MIH_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
 
     mih_index *ix = new (std::nothrow) mih_index();
@@ -544,13 +546,14 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
         }
     }
     const uint32_t lg = ceil_log2(n + 1);
-    uint64_t direct_bytes = 0, sorted_bytes = 0, max_entries = n + 1;
+    uint64_t direct_bytes = 0, sorted_bytes = 0, grouped_bytes = 0, max_entries = n + 1;
     for (uint32_t j = 0; j < m; ++j) {
         uint32_t p = lg > 3 ? lg - 3 : 1;
         if (p > ix->len[j]) p = ix->len[j];
         if (p < 1) p = 1;
         ix->dir_bits[j] = p;
-        direct_bytes += ((1ull << ix->len[j]) + 1) * 4;
+        direct_bytes += ((1ull << ix->len[j]) + 1) * 4 + std::max<uint64_t>((1ull << ix->len[j]) / 32, 1) * 4;
+        grouped_bytes += std::max<uint64_t>((1ull << ix->len[j]) / 32, 1) * 8;
         sorted_bytes += n * 4 + ((1ull << p) + 1) * 4;
         max_entries = std::max<uint64_t>(max_entries, (1ull << ix->len[j]) + 1);
     }
@@ -568,20 +571,25 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     uint64_t need = ids_bytes + temp_bytes + reserve;
     if (o.table_mode == MIH_TABLE_DIRECT) ix->table_mode = MIH_TABLE_DIRECT;
     else if (o.table_mode == MIH_TABLE_SORTED) ix->table_mode = MIH_TABLE_SORTED;
+    else if (o.table_mode == MIH_TABLE_GROUPED) ix->table_mode = MIH_TABLE_GROUPED;
     else ix->table_mode = need + direct_bytes <= budget ? MIH_TABLE_DIRECT : MIH_TABLE_SORTED;
-    need += ix->table_mode == MIH_TABLE_DIRECT ? direct_bytes : sorted_bytes;
-    if (o.codes_mode == MIH_CODES_INLINE) ix->codes_mode = MIH_CODES_INLINE;
+    need += ix->table_mode == MIH_TABLE_DIRECT ? direct_bytes
+          : ix->table_mode == MIH_TABLE_SORTED ? sorted_bytes : grouped_bytes;
+    // the offsets of a GROUPED table exist only while it is built
+    const uint64_t build_off_bytes = ix->table_mode == MIH_TABLE_GROUPED ? (max_entries + 1) * 4 : 0;
+    need += build_off_bytes;
+    if (o.codes_mode == MIH_CODES_INLINE || ix->table_mode == MIH_TABLE_GROUPED) ix->codes_mode = MIH_CODES_INLINE;
     else if (o.codes_mode == MIH_CODES_INDIRECT) ix->codes_mode = MIH_CODES_INDIRECT;
     else ix->codes_mode = need + inline_bytes <= budget ? MIH_CODES_INLINE : MIH_CODES_INDIRECT;
     if (ix->codes_mode == MIH_CODES_INLINE) need += inline_bytes;
     if (o.mem_budget_bytes && need - reserve > budget) { delete ix; return MIH_ERR_NOMEM; }
 
     mih_status st = MIH_OK;
-    Scratch tk1, tk2, ti2, tmp;
+    Scratch tk1, tk2, ti2, tmp, toff;
     do {
         hipError_t e;
         if ((e = tk1.ensure(n * 4 + 4)) != hipSuccess || (e = tk2.ensure(n * 4 + 4)) != hipSuccess ||
-            (e = ti2.ensure(n * 4 + 4)) != hipSuccess ||
+            (e = ti2.ensure(n * 4 + 4)) != hipSuccess || (e = toff.ensure(build_off_bytes)) != hipSuccess ||
             (e = tmp.ensure(std::max(mih::radix_tmp_words(n), mih::scan_tmp_words(max_entries)) * 4)) !=
                 hipSuccess) {
             st = from_hip(e);
@@ -613,6 +621,14 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
                 if (e == hipSuccess && (e = ix->alloc((void **)&occ, std::max<uint64_t>(nb / 32, 1) * 4)) == hipSuccess)
                     e = mih::occupancy_bits(off, nb, occ, s);
                 T.occ = occ;
+            } else if (ix->table_mode == MIH_TABLE_GROUPED) {
+                const uint64_t nb = 1ull << T.len;
+                uint32_t *off = (uint32_t *)toff.ptr;
+                uint64_t *grp = nullptr;
+                e = mih::bucket_offsets(keys, n, 0, off, nb, (uint32_t *)tmp.ptr, s);
+                if (e == hipSuccess && (e = ix->alloc((void **)&grp, std::max<uint64_t>(nb / 32, 1) * 8)) == hipSuccess)
+                    e = mih::group_records(off, nb, grp, s);
+                T.grp = grp;
             } else {
                 uint32_t *skeys = nullptr, *dir = nullptr;
                 const uint64_t nb = 1ull << T.dir_bits;
@@ -642,6 +658,7 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     tk2.release();
     ti2.release();
     tmp.release();
+    toff.release();
     if (st != MIH_OK) { delete ix; return st; }
     // the occupancy map pays off where the offsets array outgrows the caches
     uint32_t max_len = 0;
@@ -845,6 +862,7 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning)
     if (tuning->chunk == 0 || tuning->chunk % (64 * J) != 0 || tuning->chunk > (1u << 20))
         return MIH_ERR_INVALID;
     if (tuning->blocks_per_cu > 64 || tuning->occupancy_filter > 1) return MIH_ERR_INVALID;
+    if (tuning->sweep_shift > 32 || tuning->sweep_bits < 10 || tuning->sweep_bits > 32) return MIH_ERR_INVALID;
     std::lock_guard<std::mutex> lock(idx->mu);
     idx->tuning = *tuning;
     idx->tuning_version++;
@@ -865,6 +883,7 @@ mih_status mih_index_table(const mih_index *idx, uint32_t j, mih_table_view *vie
     view->dir_bits = idx->table_mode == MIH_TABLE_SORTED ? T.dir_bits : 0;
     view->pad = 0;
     view->occupancy = T.occ;
+    view->groups = T.grp;
     return MIH_OK;
 }
 
@@ -996,7 +1015,11 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
         for (uint32_t J : {4u, 8u, 16u}) {
             for (uint32_t mult : {8u, 32u, 128u}) {
                 if (st != MIH_OK) break;
-                mih_tuning t = {J, 64 * J * mult, 0, f};
+                mih_tuning t = idx->tuning;
+                t.probes_per_lane = J;
+                t.chunk = 64 * J * mult;
+                t.blocks_per_cu = 0;
+                t.occupancy_filter = f;
                 if ((st = mih_set_tuning(idx, &t)) != MIH_OK) break;
                 auto t0 = clk::now();
                 st = mih_knn(idx, queries, nq, k, k_per_query, oi, od, stream);

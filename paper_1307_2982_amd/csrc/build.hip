@@ -131,6 +131,28 @@ __global__ __launch_bounds__(MIH_BLOCK) void occupancy_kernel(const uint32_t *__
     }
 }
 
+// Record g of a GROUPED table: the occupancy bits of buckets 32g..32g+31
+// and, in the high half, the position of the group's first code.
+__global__ __launch_bounds__(MIH_BLOCK) void group_records_kernel(const uint32_t *__restrict__ off,
+                                                                  uint64_t nbuckets, uint64_t *grp)
+{
+    const uint64_t ngroups = (nbuckets + 31) / 32;
+    uint64_t g = (uint64_t)blockIdx.x * MIH_BLOCK + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * MIH_BLOCK;
+    for (; g < ngroups; g += stride) {
+        uint32_t word = 0;
+        const uint64_t v0 = g * 32;
+        const uint32_t first = off[v0];
+        uint32_t prev = first;
+        for (uint32_t b = 0; b < 32 && v0 + b < nbuckets; ++b) {
+            const uint32_t nxt = off[v0 + b + 1];
+            if (nxt > prev) word |= 1u << b;
+            prev = nxt;
+        }
+        grp[g] = ((uint64_t)first << 32) | word;
+    }
+}
+
 template <int W>
 __global__ __launch_bounds__(MIH_BLOCK) void gather_codes_kernel(const uint64_t *__restrict__ codes,
                                                                  const uint32_t *__restrict__ ids,
@@ -217,6 +239,12 @@ hipError_t bucket_offsets(const uint32_t *sorted_keys, uint64_t n, uint32_t shif
 hipError_t occupancy_bits(const uint32_t *off, uint64_t nbuckets, uint32_t *occ, hipStream_t s)
 {
     occupancy_kernel<<<grid_for((nbuckets + 31) / 32), MIH_BLOCK, 0, s>>>(off, nbuckets, occ);
+    return hipGetLastError();
+}
+
+hipError_t group_records(const uint32_t *off, uint64_t nbuckets, uint64_t *grp, hipStream_t s)
+{
+    group_records_kernel<<<grid_for((nbuckets + 31) / 32), MIH_BLOCK, 0, s>>>(off, nbuckets, grp);
     return hipGetLastError();
 }
 

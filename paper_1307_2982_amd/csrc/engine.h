@@ -57,7 +57,7 @@ struct mih_index {
     std::vector<void *> allocs;
     uint64_t device_bytes = 0;
     double build_ms = 0;
-    mih_tuning tuning = {4, 8192, 0, 0};
+    mih_tuning tuning = {4, 8192, 0, 0, 0, 18};
     uint32_t tuning_version = 0;
     std::mutex mu;
     std::unique_ptr<mih::Engine> batch_engine;   // reused by mih_knn calls
@@ -157,7 +157,7 @@ private:
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t graph_exec_ = nullptr;
     uint32_t graph_tuning_version_ = ~0u;
-    uint32_t round_grid_ = 0;
+    uint32_t round_grid_ = 0, sweep_grid_ = 0;
 
     std::vector<uint32_t> free_slots_;
     std::vector<SlotInfo> slot_info_;

@@ -120,7 +120,7 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
                    o_nt = take(4ull * S_), o_new = take(4ull * S_), o_done = take(4ull * S_),
                    o_ovf = take(4ull * S_), o_btau = take(4ull * S_), o_bcap = take(4ull * S_),
                    o_grp = take(sizeof(Group) * (ix_->t_all + 1)), o_ctrl = take(sizeof(Control)),
-                   o_work = take(8), o_stats = take(8 * 4), o_adm = take(sizeof(AdmitRec) * S_),
+                   o_work = take(16), o_stats = take(8 * 4), o_adm = take(sizeof(AdmitRec) * S_),
                    o_tl = take(4ull * S_), o_tc = take(4ull * S_);
     hipError_t e = hipMalloc(&dev_, used);
     if (e != hipSuccess) { dev_ = nullptr; return e; }
@@ -164,7 +164,7 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
     if ((e = hipEventCreate(&ev_a_)) != hipSuccess || (e = hipEventCreate(&ev_b_)) != hipSuccess) return e;
     // zeroed control block, counters and statistics
     if ((e = fill_u32((uint32_t *)ctrl_, sizeof(Control) / 4, 0u, s_)) != hipSuccess) return e;
-    if ((e = fill_u64((uint64_t *)work_, 1, 0ull, s_)) != hipSuccess) return e;
+    if ((e = fill_u64((uint64_t *)work_, 2, 0ull, s_)) != hipSuccess) return e;
     if ((e = fill_u64((uint64_t *)stats_, 4, 0ull, s_)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
     free_slots_.resize(S_);
@@ -182,11 +182,14 @@ void Engine::fill_args(MihArgs &A) const
     A.m = ix_->m;
     A.bits = ix_->bits;
     A.t_all = ix_->t_all;
-    A.sorted = ix_->table_mode == MIH_TABLE_SORTED;
+    A.tm = ix_->table_mode == MIH_TABLE_SORTED ? TM_SORTED
+         : ix_->table_mode == MIH_TABLE_GROUPED ? TM_GROUPED : TM_DIRECT;
     A.inline_codes = ix_->codes_mode == MIH_CODES_INLINE;
     A.chunk = ix_->tuning.chunk;
     A.J = ix_->tuning.probes_per_lane;
     A.occ_filter = ix_->tuning.occupancy_filter && ix_->table_mode == MIH_TABLE_DIRECT;
+    A.sweep_shift = ix_->tuning.sweep_shift;
+    A.sweep_bits = ix_->tuning.sweep_bits;
     A.qb = qb_;
     A.t = t_;
     A.out_ids = out_ids_;
@@ -200,6 +203,7 @@ void Engine::fill_args(MihArgs &A) const
     A.groups = groups_;
     A.ctrl = ctrl_;
     A.work = work_;
+    A.work_sweep = work_ + 1;
     A.stats = stats_;
 }
 
@@ -342,9 +346,13 @@ hipError_t Engine::capture_graph()
     if (graph_) { (void)hipGraphDestroy(graph_); graph_ = nullptr; }
     MihArgs A;
     fill_args(A);
-    uint32_t per_cu = (uint32_t)mih_round_occupancy(A.W, A.sorted, A.inline_codes, A.J);
+    uint32_t per_cu = (uint32_t)mih_round_occupancy(A.W, A.tm, A.inline_codes, A.J, false);
     if (ix_->tuning.blocks_per_cu && ix_->tuning.blocks_per_cu < per_cu) per_cu = ix_->tuning.blocks_per_cu;
     round_grid_ = cu_count() * per_cu;
+    uint32_t per_cu_sweep = (uint32_t)mih_round_occupancy(A.W, A.tm, A.inline_codes, A.J, true);
+    if (ix_->tuning.blocks_per_cu && ix_->tuning.blocks_per_cu < per_cu_sweep)
+        per_cu_sweep = ix_->tuning.blocks_per_cu;
+    sweep_grid_ = cu_count() * per_cu_sweep;
     if (!use_graph_) {
         graph_tuning_version_ = ix_->tuning_version;
         return hipSuccess;
@@ -355,6 +363,7 @@ hipError_t Engine::capture_graph()
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t e1 = mih_regroup(A, cs);
+        if (e1 == hipSuccess && A.sweep_shift) e1 = mih_sweep(A, sweep_grid_, cs);
         if (e1 == hipSuccess) e1 = mih_round(A, round_grid_, cs);
         if (e1 == hipSuccess) e1 = mih_advance(A, S_, cs);
         if (e1 == hipSuccess)
@@ -392,6 +401,7 @@ hipError_t Engine::run_round()
         fill_args(A);
         if ((e = mih_regroup(A, s_)) != hipSuccess) return e;
         if ((e = hipEventRecord(ev_a_, s_)) != hipSuccess) return e;
+        if (A.sweep_shift && (e = mih_sweep(A, sweep_grid_, s_)) != hipSuccess) return e;
         if ((e = mih_round(A, round_grid_, s_)) != hipSuccess) return e;
         if ((e = hipEventRecord(ev_b_, s_)) != hipSuccess) return e;
         if ((e = mih_advance(A, S_, s_)) != hipSuccess) return e;

@@ -211,6 +211,8 @@ struct RnnMove {
 struct TableDev {
     const uint32_t *off;     // DIRECT: [2^len + 1]
     const uint32_t *occ;     // DIRECT: [2^len / 32 (at least 1)] bit v: bucket v non-empty
+    const uint64_t *grp;     // GROUPED: [2^len / 32 (at least 1)]: bits 0..31 occupancy of
+                             // buckets 32g..32g+31, bits 32..63 position of the group's first code
     const uint32_t *keys;    // SORTED: [n]
     const uint32_t *dir;     // SORTED: [2^dir_bits + 1]
     const uint32_t *ids;     // [n]
@@ -254,6 +256,8 @@ hipError_t gather_codes(const uint64_t *codes, const uint32_t *ids, uint64_t n, 
                         uint64_t *out, hipStream_t s);
 // occ[v / 32] bit v % 32 = [off[v + 1] > off[v]] for v < nbuckets.
 hipError_t occupancy_bits(const uint32_t *off, uint64_t nbuckets, uint32_t *occ, hipStream_t s);
+// grp[g] = (off[32 g] << 32) | occupancy bits of buckets 32g..32g+31.
+hipError_t group_records(const uint32_t *off, uint64_t nbuckets, uint64_t *grp, hipStream_t s);
 
 // linscan.hip
 struct LinscanArgs {

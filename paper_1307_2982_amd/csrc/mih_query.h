@@ -5,16 +5,29 @@
 
 namespace mih {
 
+// Table layouts as the search kernel sees them.
+enum { TM_DIRECT = 0, TM_SORTED = 1, TM_GROUPED = 2 };
+
 // Active queries that share the same next step form a group; its work items
 // are the chunks of that step's shell for each of its queries, numbered
 // from item_start, query-major.
+// A group whose step has many more probes than its table has buckets per
+// cache line runs in the sweep kernel instead (ipq = 0 there): its items
+// are (key partition of 2^sweep_bits values, chunk of kSweepQueries queries).
 struct Group {
     uint32_t t;           // step to process
     uint32_t count;       // queries in the group
-    uint32_t ipq;         // work items per query: ceil(C(s_a, r') / chunk)
+    uint32_t ipq;         // work items per query: ceil(C(s_a, r') / chunk), 0 when swept
     uint32_t slot_start;  // first position of the group in the active list
     uint64_t item_start;  // first work item of the group
+    uint32_t sweep_bits;  // swept: L, the key bits enumerated inside a partition; else 0
+    uint32_t sweep_qc;    // swept: query chunks per partition
+    uint64_t sweep_start; // first sweep item of the group
 };
+
+// Queries per sweep work item, and the smallest table that is swept.
+constexpr uint32_t kSweepQueries = 64;
+constexpr uint32_t kSweepMinBits = 20;
 
 // Device-resident control block of a search engine.
 struct Control {
@@ -25,6 +38,7 @@ struct Control {
     uint32_t n_done;      // queries finished by the last advance
     uint32_t n_ovf;       // queries finished with an overflowed buffer
     uint32_t pad;
+    uint64_t sweep_items; // items of the sweep kernel in the current round
 };
 
 // One admitted query: its slot and the state it starts from.
@@ -42,11 +56,13 @@ struct MihArgs {
     uint64_t n;
     uint32_t W, m, bits;
     uint32_t t_all;           // after this step every code has been found
-    uint32_t sorted;          // SORTED tables
+    uint32_t tm;              // table layout: TM_DIRECT, TM_SORTED or TM_GROUPED
     uint32_t inline_codes;    // INLINE codes
     uint32_t chunk;           // masks per work item (multiple of 64 J)
     uint32_t J;               // masks per lane per iteration: 4, 8 or 16
     uint32_t occ_filter;      // DIRECT: test the occupancy bitmap before the offsets
+    uint32_t sweep_shift;     // sweep a group when its probes reach 2^s >> sweep_shift (0: never)
+    uint32_t sweep_bits;      // key bits enumerated inside one sweep partition
     QueryBatch qb;            // per-slot state (qb.queries is slot storage)
     uint32_t *t;              // [slots] current step of each query
     uint64_t *out_ids;        // [slots] output row of each query
@@ -60,11 +76,14 @@ struct MihArgs {
     Group *groups;            // [t_all + 1]
     Control *ctrl;
     unsigned long long *work; // work-item counter
+    unsigned long long *work_sweep; // work-item counter of the sweep kernel
     unsigned long long *stats;// [2] probes, candidates
 };
 
 hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s);
-int mih_round_occupancy(uint32_t W, bool sorted, bool inline_codes, uint32_t J);
+// The swept groups of the round (returns at once when there are none).
+hipError_t mih_sweep(const MihArgs &A, uint32_t grid, hipStream_t s);
+int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, bool sweep);
 bool mih_probes_per_lane_ok(uint32_t J);
 // Start of a round: merge survivors and new queries into the active list.
 hipError_t mih_regroup(const MihArgs &A, hipStream_t s);

@@ -79,9 +79,88 @@ struct WaveStats {
     uint64_t probes, candidates;
 };
 
-// One step of query q, masks of rank [rb, re) of shell (t mod m, t / m).
-template <int W, bool SORTED, bool INLINE, int J>
-__device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t rb, uint32_t re,
+// Substring value of the code at table position pos (INLINE codes): only
+// the one or two words that hold bits [start, start + len) are read.
+template <int W>
+__device__ __forceinline__ uint32_t entry_key(const uint64_t *codes, uint64_t pos, uint32_t start,
+                                              uint32_t len)
+{
+    const uint32_t w = start >> 6, o = start & 63;
+    const uint64_t *c = codes + pos * W + w;
+    uint64_t v = c[0] >> o;
+    if (o + len > 64) v |= c[1] << (64 - o);
+    return (uint32_t)(v & ((len >= 32) ? 0xFFFFFFFFull : ((1ull << len) - 1)));
+}
+
+// First position in [p, n) whose substring value is at least `key`, given
+// that the values from p on are sorted and that one of them is at least key
+// or the range ends at n: doubling steps, then a binary search.
+template <int W>
+__device__ __forceinline__ uint32_t gallop_at_least(const TableDev &T, uint64_t n, uint64_t key,
+                                                    uint32_t p)
+{
+    uint64_t lo = p, step = 1;
+    while (lo + step <= n && entry_key<W>(T.codes, lo + step - 1, T.start, T.len) < key) {
+        lo += step;
+        step <<= 1;
+    }
+    uint64_t hi = lo + step < n ? lo + step : n;   // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (entry_key<W>(T.codes, mid, T.start, T.len) < key) lo = mid + 1; else hi = mid;
+    }
+    return (uint32_t)lo;
+}
+
+// GROUPED tables: the bucket `key`, known to be non-empty, inside the run of
+// codes sorted by substring value, starting the search at `p`, a position
+// no later than the bucket's first code.  Returns its first position and size.  The common case
+// (a few codes per group) is settled by one window of four entries read
+// together; longer runs fall back to doubling steps and a binary search.
+// Positions at or past n compare as larger than every value.
+template <int W>
+__device__ __forceinline__ void group_scan(const TableDev &T, uint64_t n, uint32_t key, uint32_t p,
+                                           uint32_t &lo, uint32_t &cnt)
+{
+    uint32_t lt = 0, eq = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t pos = (uint64_t)p + i;
+        const uint64_t v = pos < n ? (uint64_t)entry_key<W>(T.codes, pos, T.start, T.len) : (1ull << 32);
+        lt += v < key ? 1u : 0u;
+        eq += v == key ? 1u : 0u;
+    }
+    if (lt + eq < 4) {           // the window ends inside the bucket's successor
+        lo = p + lt;
+        cnt = eq;
+        return;
+    }
+    lo = lt < 4 ? p + lt : gallop_at_least<W>(T, n, key, p + 4);
+    if (lo >= n) {               // cannot happen for an occupied bucket; stay in bounds
+        cnt = 0;
+        return;
+    }
+    const uint32_t end = gallop_at_least<W>(T, n, (uint64_t)key + 1, lo + 1);
+    cnt = end - lo;
+}
+
+// The query's words (wave-uniform) and its key in table a.
+template <int W>
+__device__ __forceinline__ uint32_t query_key(const mih::MihArgs &A, uint32_t q, uint32_t a, uint64_t (&g)[W])
+{
+#pragma unroll
+    for (int w = 0; w < W; ++w) g[w] = u64_uniform<W>(A.qb.queries[(uint64_t)q * W + w]);
+    return substring<W>(g, A.tables[a].start, A.tables[a].len);
+}
+
+// Part of step t of query q: the buckets key_base ^ mask for the masks of
+// rank [rb, re) among the `nbits`-bit masks with `rho` set bits.  A whole
+// step is key_base = the query's key, nbits = s_a, rho = t / m; one key
+// partition of a step (the sweep kernel) fixes the high bits of the key and
+// enumerates the rest.
+template <int W, int TM, bool INLINE, int J>
+__device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t key_base,
+                             uint32_t nbits, uint32_t rho, uint32_t rb, uint32_t re,
                              const uint32_t (*binom)[MIH_BINOM_N], uint32_t *stage_pos,
                              uint32_t *stage_cum, WaveStats &ws)
 {
@@ -89,27 +168,40 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
     const uint32_t m = A.m;
     const uint32_t rp = t / m, a = t - rp * m;
     const TableDev T = A.tables[a];
-    const uint32_t s = T.len;
     uint64_t g[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) g[w] = u64_uniform<W>(A.qb.queries[(uint64_t)q * W + w]);
-    const uint32_t key_q = substring<W>(g, T.start, s);
+    (void)query_key<W>(A, q, a, g);
     uint32_t tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
 
     for (uint32_t base = rb; base < re; base += MIH_WAVE * J) {
         const uint32_t r0 = base + lane * J;
         const uint32_t nmy = r0 < re ? (re - r0 < (uint32_t)J ? re - r0 : (uint32_t)J) : 0u;
         uint32_t lo[J], cnt[J], keys[J];
-        uint32_t mask = nmy ? unrank_mask(r0, rp, s, binom) : 0u;
+        uint32_t mask = nmy ? unrank_mask(r0, rho, nbits, binom) : 0u;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            keys[j] = key_q ^ mask;
-            if ((uint32_t)j + 1 < nmy && rp > 0) mask = next_mask(mask);
+            keys[j] = key_base ^ mask;
+            if ((uint32_t)j + 1 < nmy && rho > 0) mask = next_mask(mask);
         }
         // DIRECT tables with the occupancy filter: one bit per bucket says
-        // whether it holds codes; only occupied buckets read their offsets
+        // whether it holds codes; only occupied buckets read their offsets.
+        // GROUPED tables: the group record holds the same bits.
         uint32_t occ_bits = ~0u;
-        if (!SORTED && A.occ_filter) {
+        uint32_t gbase[J];
+        if (TM == mih::TM_GROUPED) {
+            occ_bits = 0;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                gbase[j] = 0;
+                if ((uint32_t)j < nmy) {
+                    const uint64_t rec = T.grp[keys[j] >> 5];
+                    const uint32_t bit = keys[j] & 31, occ = (uint32_t)rec;
+                    if ((occ >> bit) & 1u) occ_bits |= 1u << j;
+                    // every occupied bucket below this one in the group holds
+                    // at least one code: the bucket starts no earlier than here
+                    gbase[j] = (uint32_t)(rec >> 32) + __popc(occ & ((1u << bit) - 1u));
+                }
+            }
+        } else if (TM == mih::TM_DIRECT && A.occ_filter) {
             occ_bits = 0;
 #pragma unroll
             for (int j = 0; j < J; ++j)
@@ -121,13 +213,15 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
             lo[j] = 0;
             if ((uint32_t)j < nmy && ((occ_bits >> j) & 1u)) {
                 const uint32_t key = keys[j];
-                if (!SORTED) {
+                if (TM == mih::TM_GROUPED) {
+                    group_scan<W>(T, A.n, key, gbase[j], lo[j], cnt[j]);
+                } else if (TM == mih::TM_DIRECT) {
                     const uint32_t b0 = T.off[key];
                     const uint32_t b1 = T.off[(uint64_t)key + 1];
                     lo[j] = b0;
                     cnt[j] = b1 - b0;
                 } else {
-                    const uint32_t cell = key >> (s - T.dir_bits);
+                    const uint32_t cell = key >> (T.len - T.dir_bits);
                     uint32_t x0 = T.dir[cell], x1 = T.dir[(uint64_t)cell + 1];
                     // first position with keys >= key, then first with keys > key
                     uint32_t l = x0, h = x1;
@@ -213,7 +307,7 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
     }
 }
 
-template <int W, bool SORTED, bool INLINE, int J>
+template <int W, int TM, bool INLINE, int J>
 __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
 {
     __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
@@ -249,7 +343,10 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
         const uint32_t M = binom_calc(A.tables[t - rp * A.m].len, rp);
         const uint32_t rb = part * chunk;
         const uint32_t re = rb + chunk < M ? rb + chunk : M;
-        process_step<W, SORTED, INLINE, J>(A, q, t, rb, re, binom, stage_pos[wave], stage_cum[wave], ws);
+        uint64_t gq[W];
+        const uint32_t a0 = t - rp * A.m;
+        process_step<W, TM, INLINE, J>(A, q, t, query_key<W>(A, q, a0, gq), A.tables[a0].len, rp, rb, re,
+                                       binom, stage_pos[wave], stage_cum[wave], ws);
         if (G.ipq != 1) continue;
         // the whole step belonged to this wave: keep going while steps are small
         for (;;) {
@@ -259,10 +356,75 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
             const uint32_t rpn = tn / A.m;
             const uint32_t Mn = binom_calc(A.tables[tn - rpn * A.m].len, rpn);
             if (Mn > chunk) break;
-            if (Mn) process_step<W, SORTED, INLINE, J>(A, q, tn, 0, Mn, binom, stage_pos[wave],
-                                                       stage_cum[wave], ws);
+            if (Mn) {
+                const uint32_t an = tn - rpn * A.m;
+                process_step<W, TM, INLINE, J>(A, q, tn, query_key<W>(A, q, an, gq), A.tables[an].len, rpn,
+                                               0, Mn, binom, stage_pos[wave], stage_cum[wave], ws);
+            }
             t = tn;
             if (lane == 0) A.t[q] = t;
+        }
+    }
+    if (lane == 0) {
+        atomicAdd(&A.stats[0], (unsigned long long)ws.probes);
+        atomicAdd(&A.stats[1], (unsigned long long)ws.candidates);
+    }
+}
+
+// The steps of swept groups, partition-major.  The key space of table a is
+// cut into 2^(s - L) partitions of 2^L consecutive values; a work item is one
+// partition h with a chunk of the group's queries.  A query meets partition
+// h only through the masks whose high part is (key_q >> L) ^ h, i.e. the
+// L-bit masks with r' - popc((key_q >> L) ^ h) set bits; over all h these
+// are exactly the C(s, r') buckets of the step (Vandermonde's identity).
+// Consecutive items share a partition, so its occupancy bits, offsets and
+// codes come from the caches instead of costing a line per probe.
+template <int W, int TM, bool INLINE, int J>
+__global__ __launch_bounds__(MIH_BLOCK) void mih_sweep_kernel(mih::MihArgs A)
+{
+    __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
+    __shared__ uint32_t stage_pos[kWaves][MIH_WAVE * J];
+    __shared__ uint32_t stage_cum[kWaves][MIH_WAVE * J];
+    const uint64_t total = A.ctrl->sweep_items;
+    if (total == 0) return;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += MIH_BLOCK)
+        binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
+    __syncthreads();
+
+    const uint32_t n_groups = A.ctrl->n_groups;
+    WaveStats ws = {0, 0};
+    for (;;) {
+        uint64_t item = 0;
+        if (lane == 0) item = atomicAdd(A.work_sweep, 1ull);
+        item = u64_uniform<1>(__shfl(item, 0, MIH_WAVE));
+        if (item >= total) break;
+        uint32_t gl = 0, gh = n_groups;
+        while (gh - gl > 1) {
+            uint32_t mid = (gl + gh) >> 1;
+            if (A.groups[mid].sweep_start <= item) gl = mid; else gh = mid;
+        }
+        const mih::Group G = A.groups[gl];
+        if (G.sweep_qc == 0) continue;   // not a swept group (cannot own an item)
+        const uint64_t rel = item - G.sweep_start;
+        const uint32_t h = (uint32_t)(rel / G.sweep_qc);
+        const uint32_t c = (uint32_t)(rel % G.sweep_qc);
+        const uint32_t t = G.t, rp = t / A.m, a = t - rp * A.m;
+        const uint32_t L = G.sweep_bits;
+        const uint32_t low = L >= 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
+        const uint32_t hi_key = (uint32_t)((uint64_t)h << L);
+        const uint32_t i1 = (c + 1) * mih::kSweepQueries < G.count ? (c + 1) * mih::kSweepQueries : G.count;
+        for (uint32_t i = c * mih::kSweepQueries; i < i1; ++i) {
+            const uint32_t q = A.active[G.slot_start + i];
+            uint64_t g[W];
+            const uint32_t key_q = query_key<W>(A, q, a, g);
+            const uint32_t w = __popc((L >= 32 ? 0u : key_q >> L) ^ h);
+            if (w > rp) continue;
+            const uint32_t rho = rp - w;
+            const uint32_t M = rho <= L ? binom[L][rho] : 0u;
+            if (M == 0) continue;
+            process_step<W, TM, INLINE, J>(A, q, t, hi_key | (key_q & low), L, rho, 0, M, binom,
+                                           stage_pos[wave], stage_cum[wave], ws);
         }
     }
     if (lane == 0) {
@@ -323,7 +485,7 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
 {
     extern __shared__ uint32_t bins[];   // [nbins] counts, then [nbins] cursors
     __shared__ uint32_t s_active, s_groups;
-    __shared__ unsigned long long s_items;
+    __shared__ unsigned long long s_items, s_sweep;
     const uint32_t tid = threadIdx.x;
     const uint32_t nbins = A.t_all + 1;
     mih::Control *ctrl = A.ctrl;
@@ -339,27 +501,42 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
     __syncthreads();
     if (tid == 0) {
         uint32_t slot = 0, ng = 0;
-        uint64_t items = 0;
+        uint64_t items = 0, sweep_items = 0;
         for (uint32_t b = 0; b < nbins; ++b) {
             uint32_t c = bins[b];
             bins[nbins + b] = slot;
             if (!c) continue;
             const uint32_t rp = b / A.m;
-            const uint32_t M = binom_calc(A.tables[b - rp * A.m].len, rp);
-            const uint32_t ipq = (M + A.chunk - 1) / A.chunk;
+            const uint32_t s = A.tables[b - rp * A.m].len;
+            const uint32_t M = binom_calc(s, rp);
             mih::Group G;
             G.t = b;
             G.count = c;
-            G.ipq = ipq;
             G.slot_start = slot;
             G.item_start = items;
+            G.sweep_start = sweep_items;
+            // many probes per bucket line: run the step partition by partition
+            const bool sweep = A.sweep_shift != 0 && s >= mih::kSweepMinBits &&
+                               (uint64_t)c * M >= ((1ull << s) >> A.sweep_shift);
+            if (sweep) {
+                const uint32_t L = A.sweep_bits < s ? A.sweep_bits : s;
+                G.ipq = 0;
+                G.sweep_bits = L;
+                G.sweep_qc = (c + mih::kSweepQueries - 1) / mih::kSweepQueries;
+                sweep_items += (1ull << (s - L)) * G.sweep_qc;
+            } else {
+                G.ipq = (M + A.chunk - 1) / A.chunk;
+                G.sweep_bits = 0;
+                G.sweep_qc = 0;
+            }
             A.groups[ng++] = G;
             slot += c;
-            items += (uint64_t)c * ipq;
+            items += (uint64_t)c * G.ipq;
         }
         s_active = slot;
         s_groups = ng;
         s_items = items;
+        s_sweep = sweep_items;
     }
     __syncthreads();
     for (uint32_t i = tid; i < n_old; i += 1024) {
@@ -374,10 +551,12 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
         ctrl->n_active = total;
         ctrl->n_groups = s_groups;
         ctrl->total_items = s_items;
+        ctrl->sweep_items = s_sweep;
         ctrl->n_new = 0;
         ctrl->n_done = 0;
         ctrl->n_ovf = 0;
         *A.work = 0;
+        *A.work_sweep = 0;
     }
 }
 
@@ -407,31 +586,47 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_admit_kernel(mih::MihArgs A, co
 }
 
 // Kernel for (W, table mode, codes mode, J); J must be 4, 8 or 16.
-template <int W, bool SORTED, bool INLINE>
-const void *round_kernel_ptr(uint32_t J)
+template <int W, int TM, bool INLINE, int J>
+const void *kernel_of(bool sweep)
+{
+    return sweep ? reinterpret_cast<const void *>(&mih_sweep_kernel<W, TM, INLINE, J>)
+                 : reinterpret_cast<const void *>(&mih_round_kernel<W, TM, INLINE, J>);
+}
+
+template <int W, int TM, bool INLINE>
+const void *round_kernel_ptr(uint32_t J, bool sweep)
 {
     switch (J) {
-    case 4: return reinterpret_cast<const void *>(&mih_round_kernel<W, SORTED, INLINE, 4>);
-    case 8: return reinterpret_cast<const void *>(&mih_round_kernel<W, SORTED, INLINE, 8>);
-    case 16: return reinterpret_cast<const void *>(&mih_round_kernel<W, SORTED, INLINE, 16>);
+    case 4: return kernel_of<W, TM, INLINE, 4>(sweep);
+    case 8: return kernel_of<W, TM, INLINE, 8>(sweep);
+    case 16: return kernel_of<W, TM, INLINE, 16>(sweep);
     default: return nullptr;
     }
 }
 
 template <int W>
-const void *round_kernel_w(bool sorted, bool inline_codes, uint32_t J)
+const void *round_kernel_w(uint32_t tm, bool inline_codes, uint32_t J, bool sweep)
 {
-    if (sorted) return inline_codes ? round_kernel_ptr<W, true, true>(J) : round_kernel_ptr<W, true, false>(J);
-    return inline_codes ? round_kernel_ptr<W, false, true>(J) : round_kernel_ptr<W, false, false>(J);
+    switch (tm) {
+    case mih::TM_DIRECT:
+        return inline_codes ? round_kernel_ptr<W, mih::TM_DIRECT, true>(J, sweep)
+                            : round_kernel_ptr<W, mih::TM_DIRECT, false>(J, sweep);
+    case mih::TM_SORTED:
+        return inline_codes ? round_kernel_ptr<W, mih::TM_SORTED, true>(J, sweep)
+                            : round_kernel_ptr<W, mih::TM_SORTED, false>(J, sweep);
+    case mih::TM_GROUPED:   // the group scan reads the codes in table order
+        return inline_codes ? round_kernel_ptr<W, mih::TM_GROUPED, true>(J, sweep) : nullptr;
+    default: return nullptr;
+    }
 }
 
-const void *round_kernel(uint32_t W, bool sorted, bool inline_codes, uint32_t J)
+const void *round_kernel(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, bool sweep = false)
 {
     switch (W) {
-    case 1: return round_kernel_w<1>(sorted, inline_codes, J);
-    case 2: return round_kernel_w<2>(sorted, inline_codes, J);
-    case 3: return round_kernel_w<3>(sorted, inline_codes, J);
-    case 4: return round_kernel_w<4>(sorted, inline_codes, J);
+    case 1: return round_kernel_w<1>(tm, inline_codes, J, sweep);
+    case 2: return round_kernel_w<2>(tm, inline_codes, J, sweep);
+    case 3: return round_kernel_w<3>(tm, inline_codes, J, sweep);
+    case 4: return round_kernel_w<4>(tm, inline_codes, J, sweep);
     default: return nullptr;
     }
 }
@@ -444,15 +639,23 @@ bool mih_probes_per_lane_ok(uint32_t J) { return J == 4 || J == 8 || J == 16; }
 
 hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s)
 {
-    const void *k = round_kernel(A.W, A.sorted, A.inline_codes, A.J);
+    const void *k = round_kernel(A.W, A.tm, A.inline_codes, A.J);
     if (!k) return hipErrorInvalidValue;
     void *args[] = {const_cast<MihArgs *>(&A)};
     return hipLaunchKernel(k, dim3(grid), dim3(MIH_BLOCK), args, 0, s);
 }
 
-int mih_round_occupancy(uint32_t W, bool sorted, bool inline_codes, uint32_t J)
+hipError_t mih_sweep(const MihArgs &A, uint32_t grid, hipStream_t s)
 {
-    const void *k = round_kernel(W, sorted, inline_codes, J);
+    const void *k = round_kernel(A.W, A.tm, A.inline_codes, A.J, true);
+    if (!k) return hipErrorInvalidValue;
+    void *args[] = {const_cast<MihArgs *>(&A)};
+    return hipLaunchKernel(k, dim3(grid), dim3(MIH_BLOCK), args, 0, s);
+}
+
+int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, bool sweep)
+{
+    const void *k = round_kernel(W, tm, inline_codes, J, sweep);
     int blocks = 0;
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, MIH_BLOCK, 0) != hipSuccess) {
         (void)hipGetLastError();

@@ -12,7 +12,8 @@ from gpu_util import as_u32, assert_same, to_dev
 
 pytestmark = pytest.mark.gpu
 
-MODES = [("direct", "inline"), ("direct", "indirect"), ("sorted", "inline"), ("sorted", "indirect")]
+MODES = [("direct", "inline"), ("direct", "indirect"), ("sorted", "inline"), ("sorted", "indirect"),
+         ("grouped", "inline")]
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +29,7 @@ def test_build_tables_match_algorithm1(mih):
     n = 30_001
     codes = datagen.uniform_codes(n, 128, 301)
     ref = oracle.MihCpu(codes, 6)
-    for tmode in ["direct", "sorted"]:
+    for tmode in ["direct", "sorted", "grouped"]:
         idx = mih.build(to_dev(codes), 6, table_mode=tmode, codes_mode="inline")
         info = idx.info()
         assert info["sub_len"] == [22, 22, 21, 21, 21, 21]
@@ -46,6 +47,18 @@ def test_build_tables_match_algorithm1(mih):
                 occupied[values] = True
                 bits = np.unpackbits(tab["occupancy"].numpy().view(np.uint8), bitorder="little")
                 assert np.array_equal(bits[: occupied.size].astype(bool), occupied), j
+            elif tmode == "grouped":
+                # record g: first position of a value >= 32 g, and one bit per
+                # value of the group that holds codes
+                ng = max((1 << tab["len"]) // 32, 1)
+                rec = tab["groups"].numpy().view(np.uint64)
+                first = np.searchsorted(values, np.arange(ng, dtype=np.uint64) * 32)
+                assert np.array_equal(rec >> np.uint64(32), first.astype(np.uint64)), j
+                occupied = np.zeros(ng * 32, dtype=bool)
+                occupied[values] = True
+                bits = np.unpackbits((rec & np.uint64(0xFFFFFFFF)).astype("<u4").view(np.uint8),
+                                     bitorder="little")
+                assert np.array_equal(bits.astype(bool), occupied), j
             else:
                 assert np.array_equal(tab["keys"].numpy().view(np.uint32), values.astype(np.uint32))
                 p = tab["dir_bits"]
@@ -69,21 +82,30 @@ def test_mih_uniform_64_m3_all_modes(mih, tmode, cmode):
         assert_same(ids, dists, oi, od, f"{tmode}/{cmode} k={k}")
 
 
-@pytest.mark.parametrize("occ", [0, 1])
-def test_mih_launch_tunings_agree(mih, occ):
-    # Every launch tuning (probes per lane, chunk, occupancy filter) returns
-    # the same exact result; the filter only skips reads of empty buckets.
-    n, nq = 150_001, 60
+@pytest.mark.parametrize("tmode,occ,shift", [("direct", 0, 0), ("direct", 1, 0), ("grouped", 0, 0),
+                                              ("direct", 1, 9), ("grouped", 0, 9), ("sorted", 0, 9)])
+def test_mih_launch_tunings_agree(mih, tmode, occ, shift):
+    # Every launch tuning (probes per lane, chunk, occupancy filter, swept
+    # steps and their partition size) returns the same exact result and
+    # examines the same buckets: a swept step enumerates, per partition of
+    # the key space, the masks whose high part the partition fixes.
+    n, nq, m, k = 150_001, 60, 3, 50
     codes = datagen.uniform_codes(n, 64, 51)
     queries = datagen.uniform_codes(nq, 64, 52)
-    idx = mih.build(to_dev(codes), 3, table_mode="direct", codes_mode="inline")
+    idx = mih.build(to_dev(codes), m, table_mode=tmode, codes_mode="inline")
     dq = to_dev(queries)
-    oi, od = oracle.knn(codes, queries, 50)
+    oi, od = oracle.knn(codes, queries, k)
+    lens, _ = formulas.partition(64, m)
+    dk = od.reshape(nq, k)[:, -1]
+    probes = sum(sum(formulas.shell(lens[t % m], t // m) for t in range(int(d) + 1)) for d in dk)
     for J in (4, 8, 16):
         for chunk in (64 * J * 2, 64 * J * 32):
-            idx.set_tuning(J, chunk, 0, occ)
-            ids, dists = idx.knn(dq, 50)
-            assert_same(ids, dists, oi, od, f"occ={occ} J={J} chunk={chunk}")
+            for sbits in ((16, 20) if shift else (18,)):
+                idx.set_tuning(J, chunk, 0, occ, shift, sbits)
+                ids, dists, st = idx.knn(dq, k, stats=True)
+                what = f"{tmode} occ={occ} sweep={shift}/{sbits} J={J} chunk={chunk}"
+                assert_same(ids, dists, oi, od, what)
+                assert st["probes"] == probes, what
     idx.close()
 
 
@@ -122,7 +144,7 @@ def test_mih_long_codes(mih, bits, m, kind):
     n, nq = 60_000, 24
     codes = datagen.db_codes(kind, n, bits)
     queries = datagen.query_codes(kind, nq, bits)
-    for tmode, cmode in [("direct", "indirect"), ("sorted", "inline")]:
+    for tmode, cmode in [("direct", "indirect"), ("sorted", "inline"), ("grouped", "inline")]:
         idx = mih.build(to_dev(codes), m, table_mode=tmode, codes_mode=cmode)
         ids, dists = idx.knn(to_dev(queries), 10)
         oi, od = oracle.knn(codes, queries, 10)
@@ -140,13 +162,16 @@ def test_mih_per_query_k_and_k_beyond_n(mih):
     assert_same(ids, dists, oi, od, "per-query k")
 
 
-def test_mih_duplicates_overflow_rerun(mih):
+@pytest.mark.parametrize("tmode", ["auto", "grouped"])
+def test_mih_duplicates_overflow_rerun(mih, tmode):
     # 5000 copies of one code: the query equal to it finds them all in one
-    # bucket; the buffer (2048) overflows and the query is re-run exactly
+    # bucket; the buffer (2048) overflows and the query is re-run exactly.
+    # In a GROUPED table the group scan walks past long runs of equal values.
     base = datagen.uniform_codes(4, 64, 31)
-    codes = np.concatenate([np.repeat(base[:1], 5000, axis=0), datagen.uniform_codes(3000, 64, 32)])
-    queries = np.concatenate([base[:1], base[1:2], base[:1] ^ np.uint64(3)])
-    idx = mih.build(to_dev(codes), 3)
+    codes = np.concatenate([np.repeat(base[:1], 5000, axis=0), datagen.uniform_codes(3000, 64, 32),
+                            np.repeat(base[2:3] ^ np.uint64(1), 37, axis=0)])
+    queries = np.concatenate([base[:1], base[1:2], base[:1] ^ np.uint64(3), base[2:3]])
+    idx = mih.build(to_dev(codes), 3, table_mode=tmode)
     reruns = 0
     for k in [1, 100, 4096]:
         ids, dists, st = idx.knn(to_dev(queries), k, stats=True)
