@@ -356,9 +356,9 @@ def main():
                 for chunk in (64 * J * 8, 64 * J * 32, 64 * J * 128):
                     grid.append(dict(probes_per_lane=J, chunk=chunk, blocks_per_cu=0,
                                      occupancy_filter=occ, sweep_shift=0, sweep_bits=18))
-        for shift in (3, 6, 9):
-            for sbits in (16, 18, 20):
-                for J in (4, 8):
+        for shift in (2, 3, 4):
+            for sbits in (16, 18, 20, 22):
+                for J in (8,):
                     grid.append(dict(probes_per_lane=J, chunk=64 * J * 32, blocks_per_cu=0,
                                      occupancy_filter=base_t["occupancy_filter"], sweep_shift=shift,
                                      sweep_bits=sbits))

@@ -1010,23 +1010,42 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
     double best_ms = 1e300;
     // warm-up: first call sizes the engine and faults in the tables' pages
     mih_status st = mih_knn(idx, queries, nq, k, k_per_query, oi, od, stream);
+    // the grid: (filter, J, chunk) with whole steps, then partition-major
+    // sweeps of the large steps with the occupancy filter if there is one
+    std::vector<mih_tuning> grid;
     const uint32_t filters = idx->table_mode == MIH_TABLE_DIRECT ? 2 : 1;
-    for (uint32_t f = 0; f < filters; ++f) {
-        for (uint32_t J : {4u, 8u, 16u}) {
+    for (uint32_t f = 0; f < filters; ++f)
+        for (uint32_t J : {4u, 8u, 16u})
             for (uint32_t mult : {8u, 32u, 128u}) {
-                if (st != MIH_OK) break;
                 mih_tuning t = idx->tuning;
                 t.probes_per_lane = J;
                 t.chunk = 64 * J * mult;
                 t.blocks_per_cu = 0;
                 t.occupancy_filter = f;
-                if ((st = mih_set_tuning(idx, &t)) != MIH_OK) break;
-                auto t0 = clk::now();
-                st = mih_knn(idx, queries, nq, k, k_per_query, oi, od, stream);
-                const double ms = ms_since(t0);
-                if (st == MIH_OK && ms < best_ms) { best_ms = ms; best = t; }
+                t.sweep_shift = 0;
+                grid.push_back(t);
             }
-        }
+    uint32_t max_len = 0;
+    for (uint32_t j = 0; j < idx->m; ++j) max_len = std::max(max_len, idx->len[j]);
+    if (max_len >= mih::kSweepMinBits)
+        for (uint32_t J : {4u, 8u})
+            for (uint32_t bits : {18u, 20u}) {
+                mih_tuning t = idx->tuning;
+                t.probes_per_lane = J;
+                t.chunk = 64 * J * 32;
+                t.blocks_per_cu = 0;
+                t.occupancy_filter = filters - 1;
+                t.sweep_shift = 3;
+                t.sweep_bits = bits;
+                grid.push_back(t);
+            }
+    for (const mih_tuning &t : grid) {
+        if ((st = mih_set_tuning(idx, &t)) != MIH_OK) break;
+        auto t0 = clk::now();
+        st = mih_knn(idx, queries, nq, k, k_per_query, oi, od, stream);
+        const double ms = ms_since(t0);
+        if (st != MIH_OK) break;
+        if (ms < best_ms) { best_ms = ms; best = t; }
     }
     mih_status st2 = mih_set_tuning(idx, st == MIH_OK ? &best : &start);
     out.release();

@@ -120,7 +120,7 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
                    o_nt = take(4ull * S_), o_new = take(4ull * S_), o_done = take(4ull * S_),
                    o_ovf = take(4ull * S_), o_btau = take(4ull * S_), o_bcap = take(4ull * S_),
                    o_grp = take(sizeof(Group) * (ix_->t_all + 1)), o_ctrl = take(sizeof(Control)),
-                   o_work = take(16), o_stats = take(8 * 4), o_adm = take(sizeof(AdmitRec) * S_),
+                   o_work = take(8 * (1 + kSweepXcds)), o_stats = take(8 * 4), o_adm = take(sizeof(AdmitRec) * S_),
                    o_tl = take(4ull * S_), o_tc = take(4ull * S_);
     hipError_t e = hipMalloc(&dev_, used);
     if (e != hipSuccess) { dev_ = nullptr; return e; }
@@ -164,7 +164,7 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
     if ((e = hipEventCreate(&ev_a_)) != hipSuccess || (e = hipEventCreate(&ev_b_)) != hipSuccess) return e;
     // zeroed control block, counters and statistics
     if ((e = fill_u32((uint32_t *)ctrl_, sizeof(Control) / 4, 0u, s_)) != hipSuccess) return e;
-    if ((e = fill_u64((uint64_t *)work_, 2, 0ull, s_)) != hipSuccess) return e;
+    if ((e = fill_u64((uint64_t *)work_, 1 + kSweepXcds, 0ull, s_)) != hipSuccess) return e;
     if ((e = fill_u64((uint64_t *)stats_, 4, 0ull, s_)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
     free_slots_.resize(S_);

@@ -22,12 +22,15 @@ struct Group {
     uint64_t item_start;  // first work item of the group
     uint32_t sweep_bits;  // swept: L, the key bits enumerated inside a partition; else 0
     uint32_t sweep_qc;    // swept: query chunks per partition
-    uint64_t sweep_start; // first sweep item of the group
+    uint64_t sweep_start; // first sweep item of the group (in each XCD's share)
 };
 
-// Queries per sweep work item, and the smallest table that is swept.
+// Queries per sweep work item (one per lane), the smallest table that is
+// swept, and the number of XCDs the partitions are dealt to.
 constexpr uint32_t kSweepQueries = 64;
 constexpr uint32_t kSweepMinBits = 20;
+constexpr uint32_t kSweepXcds = 8;
+constexpr uint32_t kSweepBatch = 4;   // consecutive sweep items claimed at once
 
 // Device-resident control block of a search engine.
 struct Control {
@@ -38,7 +41,7 @@ struct Control {
     uint32_t n_done;      // queries finished by the last advance
     uint32_t n_ovf;       // queries finished with an overflowed buffer
     uint32_t pad;
-    uint64_t sweep_items; // items of the sweep kernel in the current round
+    uint64_t sweep_items; // items of the sweep kernel per XCD in the current round
 };
 
 // One admitted query: its slot and the state it starts from.
@@ -76,7 +79,7 @@ struct MihArgs {
     Group *groups;            // [t_all + 1]
     Control *ctrl;
     unsigned long long *work; // work-item counter
-    unsigned long long *work_sweep; // work-item counter of the sweep kernel
+    unsigned long long *work_sweep; // [kSweepXcds] work-item counters of the sweep kernel
     unsigned long long *stats;// [2] probes, candidates
 };
 

@@ -371,60 +371,296 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
     }
 }
 
-// The steps of swept groups, partition-major.  The key space of table a is
-// cut into 2^(s - L) partitions of 2^L consecutive values; a work item is one
-// partition h with a chunk of the group's queries.  A query meets partition
-// h only through the masks whose high part is (key_q >> L) ^ h, i.e. the
-// L-bit masks with r' - popc((key_q >> L) ^ h) set bits; over all h these
-// are exactly the C(s, r') buckets of the step (Vandermonde's identity).
-// Consecutive items share a partition, so its occupancy bits, offsets and
-// codes come from the caches instead of costing a line per probe.
+// Per-wave LDS state of a sweep item: its queries and staged buckets.
+template <int W, int J>
+struct SweepLds {
+    uint32_t qstart[mih::kSweepQueries + 1];   // exclusive prefix of the masks per query
+    uint32_t qkey[mih::kSweepQueries];         // partition bits | low bits of the query's key
+    uint32_t qrho[mih::kSweepQueries];         // set bits of the query's masks
+    uint32_t qslot[mih::kSweepQueries];
+    uint32_t qtau[mih::kSweepQueries];         // bound of the query (refreshed after appends)
+    uint64_t qg[mih::kSweepQueries][W];        // the query's words
+    uint32_t stage_pos[MIH_WAVE * J];
+    uint32_t stage_cum[MIH_WAVE * J];
+    uint32_t stage_q[MIH_WAVE * J];
+};
+
+// First lookup of a probe: DIRECT with the occupancy filter the bucket's
+// occupancy word, DIRECT its two offsets, GROUPED the group record,
+// SORTED the bounds of the directory cell.
+template <int TM>
+__device__ __forceinline__ void first_lookup(const TableDev &T, uint32_t occ_filter, uint32_t key,
+                                             uint32_t &pa, uint32_t &pb)
+{
+    if (TM == mih::TM_GROUPED) {
+        const uint64_t rec = T.grp[key >> 5];
+        pa = (uint32_t)rec;
+        pb = (uint32_t)(rec >> 32);
+    } else if (TM == mih::TM_DIRECT) {
+        if (occ_filter) {
+            pa = T.occ[key >> 5];
+            pb = 0;
+        } else {
+            pa = T.off[key];
+            pb = T.off[(uint64_t)key + 1];
+        }
+    } else {
+        const uint32_t cell = key >> (T.len - T.dir_bits);
+        pa = T.dir[cell];
+        pb = T.dir[(uint64_t)cell + 1];
+    }
+}
+
+// The bucket [lo, lo + cnt) of a probe from its first lookup.
+template <int W, int TM>
+__device__ __forceinline__ void second_lookup(const TableDev &T, uint64_t n, uint32_t occ_filter,
+                                              uint32_t key, uint32_t pa, uint32_t pb, uint32_t &lo,
+                                              uint32_t &cnt)
+{
+    lo = cnt = 0;
+    if (TM == mih::TM_GROUPED) {
+        const uint32_t bit = key & 31;
+        if ((pa >> bit) & 1u) group_scan<W>(T, n, key, pb + __popc(pa & ((1u << bit) - 1u)), lo, cnt);
+    } else if (TM == mih::TM_DIRECT) {
+        if (occ_filter) {
+            if ((pa >> (key & 31)) & 1u) {
+                const uint32_t b0 = T.off[key];
+                lo = b0;
+                cnt = T.off[(uint64_t)key + 1] - b0;
+            }
+        } else {
+            lo = pa;
+            cnt = pb - pa;
+        }
+    } else {
+        uint32_t l = pa, h = pb;
+        while (l < h) {
+            const uint32_t mid = l + ((h - l) >> 1);
+            if (T.keys[mid] < key) l = mid + 1; else h = mid;
+        }
+        uint32_t e = l;
+        h = pb;
+        while (e < h) {
+            const uint32_t mid = e + ((h - e) >> 1);
+            if (T.keys[mid] <= key) e = mid + 1; else h = mid;
+        }
+        lo = l;
+        cnt = e - l;
+    }
+}
+
+// One sweep item: partition h of the key space of table a (values whose
+// high s - L bits equal h) for up to kSweepQueries queries of a group at
+// step t.  A query meets partition h only through the L-bit masks with
+// r' - popc((key_q >> L) ^ h) set bits; over all h these are exactly the
+// C(s, r') buckets of the step (Vandermonde's identity).  The masks of all
+// the item's queries form one flat list that the lanes share, J per lane
+// per block, so that a query with a handful of masks in this partition does
+// not leave the wave idle.  Candidates keep their query; appends use one
+// atomic each, and the bound of each query with new candidates is
+// tightened once per block.
+template <int W, int TM, bool INLINE, int J>
+__device__ void sweep_item(const mih::MihArgs &A, const mih::Group &G, uint32_t h, uint32_t c,
+                           const uint32_t (*binom)[MIH_BINOM_N], SweepLds<W, J> &S, WaveStats &ws)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t t = G.t, rp = t / A.m, a = t - rp * A.m;
+    const TableDev T = A.tables[a];
+    const uint32_t L = G.sweep_bits;
+    const uint32_t low = L >= 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
+    const uint32_t i0 = c * mih::kSweepQueries;
+    const uint32_t nq = G.count - i0 < mih::kSweepQueries ? G.count - i0 : mih::kSweepQueries;
+
+    // lane i: query i of the chunk, its part of this partition
+    uint32_t M = 0;
+    if (lane < nq) {
+        const uint32_t q = A.active[G.slot_start + i0 + lane];
+        uint64_t g[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) g[w] = A.qb.queries[(uint64_t)q * W + w];
+        const uint32_t key = substring<W>(g, T.start, T.len);
+        const uint32_t wgt = __popc((L >= 32 ? 0u : key >> L) ^ h);
+        const uint32_t rho = wgt <= rp ? rp - wgt : 0xFFFFFFFFu;
+        M = rho <= L ? binom[L][rho] : 0u;
+        S.qkey[lane] = (uint32_t)((uint64_t)h << L) | (key & low);
+        S.qrho[lane] = rho <= L ? rho : 0u;
+        S.qslot[lane] = q;
+        S.qtau[lane] = load_relaxed(A.qb.tau + q);
+#pragma unroll
+        for (int w = 0; w < W; ++w) S.qg[lane][w] = g[w];
+    }
+    const uint32_t incl = wave_inclusive_sum(M);
+    S.qstart[lane] = incl - M;
+    if (lane == MIH_WAVE - 1) S.qstart[MIH_WAVE] = incl;
+    wave_lds_sync();
+    const uint32_t total = S.qstart[MIH_WAVE];
+    ws.probes += total;
+
+    for (uint32_t base = 0; base < total; base += MIH_WAVE * J) {
+        const uint32_t f0 = base + lane * J;
+        const uint32_t nmy = f0 < total ? (total - f0 < (uint32_t)J ? total - f0 : (uint32_t)J) : 0u;
+        uint32_t keys[J], qi[J], lo[J], cnt[J];
+        uint32_t cur = 0, mask = 0;
+        if (nmy) {
+            // the query whose masks contain flat index f0: last start <= f0
+            uint32_t l = 0, hh = MIH_WAVE;
+            while (hh - l > 1) {
+                const uint32_t mid = (l + hh) >> 1;
+                if (S.qstart[mid] <= f0) l = mid; else hh = mid;
+            }
+            cur = l;
+            mask = unrank_mask(f0 - S.qstart[cur], S.qrho[cur], L, binom);
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            keys[j] = S.qkey[cur] ^ mask;
+            qi[j] = cur;
+            if ((uint32_t)j + 1 < nmy) {
+                const uint32_t f = f0 + j + 1;
+                if (f < S.qstart[cur + 1]) {
+                    mask = next_mask(mask);
+                } else {
+                    while (S.qstart[cur + 1] <= f) ++cur;   // f < total, so this stops
+                    mask = (1u << S.qrho[cur]) - 1u;        // the first mask of that query
+                }
+            }
+        }
+        uint32_t pa[J], pb[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            pa[j] = pb[j] = 0;
+            if ((uint32_t)j < nmy) first_lookup<TM>(T, A.occ_filter, keys[j], pa[j], pb[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            lo[j] = cnt[j] = 0;
+            if ((uint32_t)j < nmy) second_lookup<W, TM>(T, A.n, A.occ_filter, keys[j], pa[j], pb[j], lo[j], cnt[j]);
+        }
+        // stage the non-empty buckets with their query
+        uint32_t ne = 0, tc = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) { ne += cnt[j] ? 1u : 0u; tc += cnt[j]; }
+        const uint32_t ne_incl = wave_inclusive_sum(ne);
+        const uint32_t tc_incl = wave_inclusive_sum(tc);
+        const uint32_t NE = __shfl(ne_incl, MIH_WAVE - 1, MIH_WAVE);
+        const uint32_t TC = __shfl(tc_incl, MIH_WAVE - 1, MIH_WAVE);
+        uint32_t p = ne_incl - ne, cc = tc_incl - tc;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (cnt[j]) {
+                S.stage_pos[p] = lo[j];
+                S.stage_cum[p] = cc;
+                S.stage_q[p] = qi[j];
+                ++p;
+                cc += cnt[j];
+            }
+        }
+        wave_lds_sync();
+        ws.candidates += TC;
+
+        uint64_t touched = 0;   // queries of the item that received candidates
+        for (uint32_t e0 = 0; e0 < TC; e0 += MIH_WAVE) {
+            const uint32_t e = e0 + lane;
+            const bool live = e < TC;
+            uint32_t bl = 0, bh = NE;
+            while (bh - bl > 1) {
+                const uint32_t mid = (bl + bh) >> 1;
+                if (S.stage_cum[mid] <= e) bl = mid; else bh = mid;
+            }
+            bool keep = false;
+            if (live) {
+                const uint32_t pos = S.stage_pos[bl] + (e - S.stage_cum[bl]);
+                const uint32_t k = S.stage_q[bl];
+                uint64_t code[W], g[W];
+                uint32_t id = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) g[w] = S.qg[k][w];
+                if (INLINE) {
+                    load_code<W>(T.codes + (uint64_t)pos * W, code);
+                } else {
+                    id = T.ids[pos];
+                    load_code<W>(A.codes + (uint64_t)id * W, code);
+                }
+                const uint32_t d = hamming<W>(code, g);
+                keep = d <= S.qtau[k];
+                if (keep) {
+                    uint64_t x[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) x[w] = code[w] ^ g[w];
+                    for (uint32_t j = 0; j < A.m; ++j) {
+                        if (j == a) continue;
+                        const uint32_t dj = __popc(substring<W>(x, A.tables[j].start, A.tables[j].len));
+                        if (j < a ? dj <= rp : dj < rp) { keep = false; break; }
+                    }
+                }
+                if (keep) {
+                    if (INLINE) id = T.ids[pos];
+                    const uint32_t q = S.qslot[k];
+                    const uint32_t slot = atomicAdd(&A.qb.count[q], 1u);
+                    if (slot < A.qb.cap[q]) A.qb.buf[A.qb.buf_off[q] + slot] = ((uint64_t)d << 32) | id;
+                    atomicAdd(&A.qb.hist[(uint64_t)q * (A.qb.bits + 1) + d], 1u);
+                    touched |= 1ull << k;
+                }
+            }
+        }
+        // tighten the bound of every query with new candidates (wave-wide)
+        uint64_t tq = touched;
+#pragma unroll
+        for (int sh = 1; sh < MIH_WAVE; sh <<= 1) tq |= (uint64_t)__shfl_xor((long long)tq, sh, MIH_WAVE);
+        tq = u64_uniform<1>(tq);
+        while (tq) {
+            const uint32_t k = (uint32_t)__ffsll((long long)tq) - 1;
+            tq &= tq - 1;
+            const uint32_t nt = tighten_tau(A.qb, S.qslot[k], S.qtau[k]);
+            if (lane == 0) S.qtau[k] = nt;
+        }
+        wave_lds_sync();
+    }
+}
+
+// The steps of swept groups, partition-major over the key space of their
+// table.  Partition h goes to XCD h mod 8 (workgroups are dispatched to the
+// eight XCDs in turn), so that the items of one partition, which read the
+// same occupancy words, offsets and codes, share that XCD's L2; a wave
+// first drains its own XCD's items, then helps the others.
 template <int W, int TM, bool INLINE, int J>
 __global__ __launch_bounds__(MIH_BLOCK) void mih_sweep_kernel(mih::MihArgs A)
 {
     __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
-    __shared__ uint32_t stage_pos[kWaves][MIH_WAVE * J];
-    __shared__ uint32_t stage_cum[kWaves][MIH_WAVE * J];
-    const uint64_t total = A.ctrl->sweep_items;
-    if (total == 0) return;
+    __shared__ SweepLds<W, J> lds[kWaves];
+    const uint64_t per_xcd = A.ctrl->sweep_items;
+    if (per_xcd == 0) return;
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += MIH_BLOCK)
         binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
     __syncthreads();
 
     const uint32_t n_groups = A.ctrl->n_groups;
+    const uint32_t home = blockIdx.x % mih::kSweepXcds;
     WaveStats ws = {0, 0};
-    for (;;) {
-        uint64_t item = 0;
-        if (lane == 0) item = atomicAdd(A.work_sweep, 1ull);
-        item = u64_uniform<1>(__shfl(item, 0, MIH_WAVE));
-        if (item >= total) break;
-        uint32_t gl = 0, gh = n_groups;
-        while (gh - gl > 1) {
-            uint32_t mid = (gl + gh) >> 1;
-            if (A.groups[mid].sweep_start <= item) gl = mid; else gh = mid;
-        }
-        const mih::Group G = A.groups[gl];
-        if (G.sweep_qc == 0) continue;   // not a swept group (cannot own an item)
-        const uint64_t rel = item - G.sweep_start;
-        const uint32_t h = (uint32_t)(rel / G.sweep_qc);
-        const uint32_t c = (uint32_t)(rel % G.sweep_qc);
-        const uint32_t t = G.t, rp = t / A.m, a = t - rp * A.m;
-        const uint32_t L = G.sweep_bits;
-        const uint32_t low = L >= 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
-        const uint32_t hi_key = (uint32_t)((uint64_t)h << L);
-        const uint32_t i1 = (c + 1) * mih::kSweepQueries < G.count ? (c + 1) * mih::kSweepQueries : G.count;
-        for (uint32_t i = c * mih::kSweepQueries; i < i1; ++i) {
-            const uint32_t q = A.active[G.slot_start + i];
-            uint64_t g[W];
-            const uint32_t key_q = query_key<W>(A, q, a, g);
-            const uint32_t w = __popc((L >= 32 ? 0u : key_q >> L) ^ h);
-            if (w > rp) continue;
-            const uint32_t rho = rp - w;
-            const uint32_t M = rho <= L ? binom[L][rho] : 0u;
-            if (M == 0) continue;
-            process_step<W, TM, INLINE, J>(A, q, t, hi_key | (key_q & low), L, rho, 0, M, binom,
-                                           stage_pos[wave], stage_cum[wave], ws);
+    for (uint32_t k = 0; k < mih::kSweepXcds; ++k) {
+        const uint32_t x = (home + k) % mih::kSweepXcds;
+        for (;;) {
+            // kSweepBatch consecutive items per claim: fewer atomics on the
+            // XCD's counter, and the items of a claim share a partition
+            uint64_t first = 0;
+            if (lane == 0) first = atomicAdd(A.work_sweep + x, (unsigned long long)mih::kSweepBatch);
+            first = u64_uniform<1>(__shfl(first, 0, MIH_WAVE));
+            if (first >= per_xcd) break;
+            const uint64_t last = first + mih::kSweepBatch < per_xcd ? first + mih::kSweepBatch : per_xcd;
+            for (uint64_t item = first; item < last; ++item) {
+                uint32_t gl = 0, gh = n_groups;
+                while (gh - gl > 1) {
+                    const uint32_t mid = (gl + gh) >> 1;
+                    if (A.groups[mid].sweep_start <= item) gl = mid; else gh = mid;
+                }
+                const mih::Group G = A.groups[gl];
+                if (G.sweep_qc == 0) continue;   // not a swept group (cannot own an item)
+                const uint64_t rel = item - G.sweep_start;
+                const uint32_t h = (uint32_t)(rel / G.sweep_qc) * mih::kSweepXcds + x;
+                const uint32_t c = (uint32_t)(rel % G.sweep_qc);
+                sweep_item<W, TM, INLINE, J>(A, G, h, c, binom, lds[wave], ws);
+            }
         }
     }
     if (lane == 0) {
@@ -519,11 +755,12 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
             const bool sweep = A.sweep_shift != 0 && s >= mih::kSweepMinBits &&
                                (uint64_t)c * M >= ((1ull << s) >> A.sweep_shift);
             if (sweep) {
-                const uint32_t L = A.sweep_bits < s ? A.sweep_bits : s;
+                // at least kSweepXcds partitions: one share per XCD
+                const uint32_t L = A.sweep_bits < s - 3 ? A.sweep_bits : s - 3;
                 G.ipq = 0;
                 G.sweep_bits = L;
                 G.sweep_qc = (c + mih::kSweepQueries - 1) / mih::kSweepQueries;
-                sweep_items += (1ull << (s - L)) * G.sweep_qc;
+                sweep_items += ((1ull << (s - L)) / mih::kSweepXcds) * G.sweep_qc;   // per XCD
             } else {
                 G.ipq = (M + A.chunk - 1) / A.chunk;
                 G.sweep_bits = 0;
@@ -556,7 +793,7 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
         ctrl->n_done = 0;
         ctrl->n_ovf = 0;
         *A.work = 0;
-        *A.work_sweep = 0;
+        for (uint32_t x = 0; x < mih::kSweepXcds; ++x) A.work_sweep[x] = 0;
     }
 }
 
