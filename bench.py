@@ -64,8 +64,9 @@ def parse():
     ap.add_argument("--m-sweep", default="",
                     help="comma-separated extra m values to build and time (e.g. 3,4)")
     ap.add_argument("--rnn", type=int, default=None,
-                    help="radius of the r-neighbour leg (default 10 per 64 bits of code)")
+                    help="radius of the r-neighbour leg (default: the median k-th nearest distance)")
     ap.add_argument("--no-rnn", action="store_true", help="skip the r-neighbour leg")
+    ap.add_argument("--no-approx", action="store_true", help="skip the approximate-search leg")
     ap.add_argument("--choose-m", action="store_true",
                     help="also pick m by timing candidates on 1000 database rows (Section 6)")
     ap.add_argument("--gather-calib", type=float, default=0.0,
@@ -457,7 +458,12 @@ def main():
     # ---------------- r-neighbour search: MIH vs linear scan, same queries
     rnn = None
     if not args.no_rnn:
-        R = args.rnn if args.rnn is not None else 10 * W
+        # default radius: the median distance of the last of each query's k
+        # nearest codes, so that a query has about k r-neighbours
+        kth = dists.reshape(-1).cpu().numpy().view(np.uint32)
+        if not mixed_k:
+            kth = kth.reshape(nq, -1)[:, -1]
+        R = args.rnn if args.rnn is not None else int(np.median(kth[kth != 0xFFFFFFFF]))
         idx.rnn(dq, R)
         torch.cuda.synchronize()
         rms = []
@@ -483,6 +489,34 @@ def main():
         log(f"r-neighbours r={R}: MIH {r_ms:.1f} ms ({rnn['mih_queries_per_s']:,.0f} q/s), "
             f"{rnn['results_per_query']:.1f} results/query; linscan {rnn.get('linscan_ms')} ms, "
             f"same={rnn.get('parity_with_linscan')}")
+
+    # ---------------- approximate variants (Section 7): speed and recall
+    approx = None
+    if not args.no_approx:
+        approx = []
+        exact = ids.reshape(-1).cpu().numpy().view(np.uint32)
+        off = np.concatenate([[0], np.cumsum(k_list.astype(np.int64))])
+        kth = dists.reshape(-1).cpu().numpy().view(np.uint32)[off[1:] - 1]
+        med = int(np.median(kth[kth != 0xFFFFFFFF])) if nq else 0
+        cand = stats[-1]["candidates"] / max(nq, 1)
+        for max_radius, budget in [(med - 2, 0), (med - 1, 0), (None, int(cand / 10)), (None, int(cand / 3))]:
+            idx.knn_approx(dq, k_arg, max_radius=max_radius, max_candidates=budget)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ai, ad, ast = idx.knn_approx(dq, k_arg, max_radius=max_radius, max_candidates=budget, stats=True)
+            torch.cuda.synchronize()
+            a_ms = (time.perf_counter() - t) * 1e3
+            got = ai.reshape(-1).cpu().numpy().view(np.uint32)
+            hits = 0
+            for q in range(nq):
+                e = exact[off[q]:off[q + 1]]
+                hits += len(np.intersect1d(got[off[q]:off[q + 1]], e[e != 0xFFFFFFFF]))
+            recall = hits / max(1, int((exact != 0xFFFFFFFF).sum()))
+            approx.append({"max_radius": max_radius, "max_candidates": budget, "ms": round(a_ms, 2),
+                           "queries_per_s": round(nq / (a_ms / 1e3), 1), "recall": round(recall, 4),
+                           "candidates_per_query": ast["candidates"] / max(nq, 1)})
+            log(f"approximate radius={max_radius} budget={budget}: {a_ms:.1f} ms "
+                f"({nq / (a_ms / 1e3):,.0f} q/s), recall {recall:.4f}")
 
     # ---------------- CPU oracle: bounded sample, also a full-size parity check
     cpu = None
@@ -561,6 +595,7 @@ def main():
         "serving": serving,
         "linscan": lin,
         "rnn": rnn,
+        "approximate": approx,
         "cpu_baseline": cpu,
         "parity": {"mih_vs_oracle_sample": parity_oracle,
                    "mih_vs_linscan_all": lin["parity_with_mih"] if lin else None},

@@ -84,6 +84,14 @@ typedef struct mih_build_opts {
     mih_table_mode table_mode;
     mih_codes_mode codes_mode;
     uint64_t mem_budget_bytes;   /* 0: the device memory free at build time */
+    const uint16_t *bit_order;   /* host [bits] or NULL.  Substring optimisation
+                                    (Section 5.4): a permutation of the code bits;
+                                    substring j is made of the code bits
+                                    bit_order[start_j .. start_j + s_j), and bit
+                                    k of its key is code bit bit_order[start_j + k].
+                                    NULL: consecutive bits (bit_order[p] = p).
+                                    Results never depend on it; speed may.  Not
+                                    retained after the call. */
 } mih_build_opts;
 
 typedef struct mih_index mih_index;   /* opaque, owned by the library */
@@ -98,6 +106,8 @@ typedef struct mih_index_info {
     uint32_t dir_bits[MIH_M_MAX]; /* SORTED: directory bits per table       */
     uint64_t device_bytes;        /* device memory held by the index        */
     double build_ms;              /* wall time of mih_build                 */
+    uint16_t bit_order[256];      /* the bit order of the substrings (the
+                                     identity unless one was given)         */
 } mih_index_info;
 
 /* Device views of one table, for inspection and tests.  Pointers are owned
@@ -194,6 +204,20 @@ mih_status linscan_knn_ex(const uint64_t *codes, uint64_t n, uint32_t bits,
                           const uint64_t *queries, uint32_t nq, uint32_t k,
                           const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
                           void *stream, mih_scan_stats *stats);
+
+/* Approximate kNN (Section 7): Algorithm 3 stopped early, returning the k
+ * best of the codes met so far.
+ *   max_radius      stop after the step that covers this radius, even if
+ *                   fewer than k codes lie within it (every code within
+ *                   max_radius is still found); 0xFFFFFFFF: no limit
+ *   max_candidates  stop after the step during which this many distinct
+ *                   codes have been met; 0: no limit
+ * With neither limit reached the answer is mih_knn's.  Rows with fewer than
+ * k codes met are padded with MIH_SENTINEL.  Other arguments as mih_knn_ex. */
+mih_status mih_knn_approx(const mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
+                          const uint32_t *k_per_query, uint32_t max_radius, uint32_t max_candidates,
+                          uint32_t *out_ids, uint32_t *out_dists, void *stream,
+                          mih_query_stats *stats);
 
 /* Release an index and its device memory.  NULL is ignored. */
 void mih_free(mih_index *idx);
@@ -331,6 +355,27 @@ mih_status mih_choose_m(const uint64_t *codes, uint64_t n, uint32_t bits, const 
                         uint32_t nq, uint32_t k, const uint32_t *candidates, uint32_t ncand,
                         const mih_build_opts *opts, void *stream, uint32_t *best_m,
                         mih_m_trial *trials, uint32_t *ntrials);
+
+/* ---- Substring optimisation (Section 5.4) ------------------------------
+ *
+ * Co-occurrence counts of the code bits over n sample codes:
+ *   device codes  [n][bits/64]
+ *   host counts   [bits * bits]: counts[i * bits + j] = number of codes with
+ *                 bits i and j both set (the diagonal holds the bit counts)
+ * n < 2^31.  Errors: MIH_ERR_INVALID for NULL counts or bad bits. */
+mih_status mih_bit_cooccurrence(const uint64_t *codes, uint64_t n, uint32_t bits, void *stream,
+                                uint32_t *counts);
+
+/* The greedy bit order of Section 5.4, from the counts above (host only).
+ * With |Pearson correlation| between bits taken from the counts (0 for a
+ * constant bit): substring 0 starts with first_bit; substring j starts with
+ * the unused bit most correlated with the first bit of substring j - 1; then
+ * the substrings, in turn, take the unused bit whose largest correlation
+ * with the bits they already hold is smallest, until each has its length
+ * (floor or ceil of bits / m, longer ones first).  Ties go to the lowest bit.
+ *   host bit_order [bits]: the order for mih_build_opts.bit_order. */
+mih_status mih_greedy_bit_order(const uint32_t *counts, uint64_t n, uint32_t bits, uint32_t m,
+                                uint32_t first_bit, uint16_t *bit_order);
 
 /* ---- Serving: continuous batching over a built index ------------------
  *

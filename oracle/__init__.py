@@ -13,7 +13,11 @@ Contents:
 * ``brute``: an independent pure-Python brute force for tiny inputs.
 * ``MihCpu``: a literal single-threaded multi-index hashing (Algorithms 1, 2
   and 3 with the paper's bitstring de-duplication, ``mih_cpu.c``), a second
-  test subject used to check the reading of the algorithm.
+  test subject used to check the reading of the algorithm; with early
+  stopping (``knn_approx``) it is the reference of the approximate variants
+  of Section 7.
+* ``substrings``: the substring optimisation of Section 5.4 (bit
+  co-occurrence counts and the greedy bit order).
 * ``formulas``: the paper's closed forms (Eq. 1, 5, 6, 7, the memory formula
   of Section 6 and the q / log2 n heuristic of Section 3.1).
 
@@ -74,6 +78,8 @@ def _lib():
         L.mihcpu_free.restype = None
         L.mihcpu_knn.argtypes = [vp, vp, u32, vp, vp, ctypes.POINTER(_Stats)]
         L.mihcpu_knn.restype = i32
+        L.mihcpu_knn_approx.argtypes = [vp, vp, u32, u32, ctypes.c_uint64, vp, vp, ctypes.POINTER(_Stats)]
+        L.mihcpu_knn_approx.restype = i32
         L.mihcpu_rnn.argtypes = [vp, vp, u32, vp, vp, u64, ctypes.POINTER(_Stats)]
         L.mihcpu_rnn.restype = ctypes.c_int64
         L.mihcpu_partition.argtypes = [u32, u32, vp, vp]
@@ -207,6 +213,21 @@ class MihCpu:
             raise MemoryError("MIH-CPU out of memory")
         stats = {f: getattr(st, f) for f, _ in _Stats._fields_}
         return ids[:k].copy(), dists[:k].copy(), stats
+
+    def knn_approx(self, query, k: int, max_step: int | None = None, max_found: int = 0):
+        """Algorithm 3 stopped after the step covering radius max_step, or
+        after the step in which max_found distinct codes have been met
+        (Section 7); the k best codes met."""
+        q = np.ascontiguousarray(query, dtype=np.uint64).reshape(-1)
+        ids = np.empty(max(k, 1), dtype=np.uint32)
+        dists = np.empty(max(k, 1), dtype=np.uint32)
+        st = _Stats()
+        rc = _lib().mihcpu_knn_approx(self._ix, q.ctypes.data, k,
+                                      0xFFFFFFFF if max_step is None else max_step, max_found,
+                                      ids.ctypes.data, dists.ctypes.data, ctypes.byref(st))
+        if rc != 0:
+            raise MemoryError("MIH-CPU out of memory")
+        return ids[:k].copy(), dists[:k].copy()
 
     def rnn(self, query, r: int):
         q = np.ascontiguousarray(query, dtype=np.uint64).reshape(-1)

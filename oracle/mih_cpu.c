@@ -204,8 +204,24 @@ static void probe_shell(visit_ctx *C, uint32_t j, uint64_t v, uint32_t rho)
  * Algorithm 3 for one query.  Writes min(k, n) results in (d, id) order to
  * ids/dists and pads up to k with the sentinel.  Returns 0, or -1 on no memory.
  */
+/*
+ * Algorithm 3 for one query, optionally stopped early (the approximate
+ * variants of Section 7): after the step that covers radius max_step
+ * (UINT32_MAX: no limit), or after the step during which the number of
+ * distinct codes met reaches max_found (0: no limit).  Returns the k best
+ * of the codes met, in (d, id) order, sentinel-padded.
+ */
+int mihcpu_knn_approx(const mihcpu_index *ix, const uint64_t *g, uint32_t k, uint32_t max_step,
+                      uint64_t max_found, uint32_t *ids, uint32_t *dists, mihcpu_stats *st);
+
 int mihcpu_knn(const mihcpu_index *ix, const uint64_t *g, uint32_t k, uint32_t *ids,
                uint32_t *dists, mihcpu_stats *st)
+{
+    return mihcpu_knn_approx(ix, g, k, 0xFFFFFFFFu, 0, ids, dists, st);
+}
+
+int mihcpu_knn_approx(const mihcpu_index *ix, const uint64_t *g, uint32_t k, uint32_t max_step,
+                      uint64_t max_found, uint32_t *ids, uint32_t *dists, mihcpu_stats *st)
 {
     mihcpu_stats local;
     if (!st) st = &local;
@@ -235,6 +251,8 @@ int mihcpu_knn(const mihcpu_index *ix, const uint64_t *g, uint32_t k, uint32_t *
         for (uint32_t d = 0; d < r && d <= ix->bits; ++d) within += count_d[d];
         if (within >= k) break;
         if (rp > maxlen) break;   /* every table searched over its whole length */
+        if (max_step != 0xFFFFFFFFu && r > max_step) break;   /* radius max_step covered */
+        if (max_found && C.nfound >= max_found) break;        /* enough distinct codes met */
     }
     st->radius = r;
 

@@ -36,7 +36,7 @@ class MihError(RuntimeError):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("table_mode", ctypes.c_int), ("codes_mode", ctypes.c_int),
-                ("mem_budget_bytes", ctypes.c_uint64)]
+                ("mem_budget_bytes", ctypes.c_uint64), ("bit_order", ctypes.c_void_p)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -44,7 +44,7 @@ class IndexInfo(ctypes.Structure):
                 ("table_mode", ctypes.c_uint32), ("codes_mode", ctypes.c_uint32),
                 ("sub_len", ctypes.c_uint32 * 64), ("sub_start", ctypes.c_uint32 * 64),
                 ("dir_bits", ctypes.c_uint32 * 64), ("device_bytes", ctypes.c_uint64),
-                ("build_ms", ctypes.c_double)]
+                ("build_ms", ctypes.c_double), ("bit_order", ctypes.c_uint16 * 256)]
 
 
 class TableView(ctypes.Structure):
@@ -105,7 +105,8 @@ class RnnView(ctypes.Structure):
 
 EXPORTED = ["mih_build", "mih_knn", "mih_knn_ex", "linscan_knn", "linscan_knn_ex", "mih_free",
             "mih_rnn", "mih_rnn_ex", "linscan_rnn", "mih_rnn_result_view", "mih_rnn_result_free",
-            "mih_model_cost", "mih_model_radius", "mih_choose_m",
+            "mih_knn_approx", "mih_model_cost", "mih_model_radius", "mih_choose_m", "mih_bit_cooccurrence",
+            "mih_greedy_bit_order",
             "mih_status_str", "mih_index_get_info", "mih_index_table", "mih_get_tuning",
             "mih_set_tuning", "mih_autotune", "mih_server_create", "mih_server_submit", "mih_server_step",
             "mih_server_poll", "mih_server_get_stats", "mih_server_destroy"]
@@ -133,6 +134,8 @@ def load():
     L.mih_knn.restype = i32
     L.mih_knn_ex.argtypes = [vp, vp, u32, u32, vp, vp, vp, vp, ctypes.POINTER(QueryStats)]
     L.mih_knn_ex.restype = i32
+    L.mih_knn_approx.argtypes = [vp, vp, u32, u32, vp, u32, u32, vp, vp, vp, ctypes.POINTER(QueryStats)]
+    L.mih_knn_approx.restype = i32
     L.linscan_knn.argtypes = [vp, u64, u32, vp, u32, u32, vp, vp, vp, vp]
     L.linscan_knn.restype = i32
     L.linscan_knn_ex.argtypes = [vp, u64, u32, vp, u32, u32, vp, vp, vp, vp, ctypes.POINTER(ScanStats)]
@@ -156,6 +159,10 @@ def load():
     L.mih_choose_m.argtypes = [vp, u64, u32, vp, u32, u32, vp, u32, ctypes.POINTER(BuildOpts), vp,
                                ctypes.POINTER(u32), ctypes.POINTER(MTrial), ctypes.POINTER(u32)]
     L.mih_choose_m.restype = i32
+    L.mih_bit_cooccurrence.argtypes = [vp, u64, u32, vp, vp]
+    L.mih_bit_cooccurrence.restype = i32
+    L.mih_greedy_bit_order.argtypes = [vp, u64, u32, u32, u32, vp]
+    L.mih_greedy_bit_order.restype = i32
     L.mih_status_str.argtypes = [i32]
     L.mih_status_str.restype = ctypes.c_char_p
     L.mih_index_get_info.argtypes = [vp, ctypes.POINTER(IndexInfo)]
@@ -255,7 +262,7 @@ class Index:
                 "codes_mode": {1: "inline", 2: "indirect"}.get(inf.codes_mode, inf.codes_mode),
                 "sub_len": list(inf.sub_len[:m]), "sub_start": list(inf.sub_start[:m]),
                 "dir_bits": list(inf.dir_bits[:m]), "device_bytes": inf.device_bytes,
-                "build_ms": inf.build_ms}
+                "build_ms": inf.build_ms, "bit_order": list(inf.bit_order[:inf.bits])}
 
     def get_tuning(self) -> dict:
         t = Tuning()
@@ -325,6 +332,25 @@ class Index:
         out = _take_rnn(h, queries.device)
         return (*out, st.as_dict()) if stats else out
 
+    def knn_approx(self, queries: torch.Tensor, k, max_radius: int | None = None,
+                   max_candidates: int = 0, stats: bool = False):
+        """Approximate kNN (Section 7): stop after the step covering
+        max_radius, or once max_candidates distinct codes were met."""
+        queries = _codes_arg(queries, "queries")
+        if queries.shape[1] != self.codes.shape[1]:
+            raise ValueError("queries and codes differ in length")
+        nq = queries.shape[0]
+        kk, kt, kl = _k_arg(k, nq, queries.device)
+        ids, dists, total = _outputs(nq, kk, kl, queries.device)
+        st = QueryStats()
+        rc = load().mih_knn_approx(self._h, queries.data_ptr(), nq, kk,
+                                   kt.data_ptr() if kt is not None else None,
+                                   0xFFFFFFFF if max_radius is None else max_radius, max_candidates,
+                                   ids.data_ptr(), dists.data_ptr(), _stream(), ctypes.byref(st))
+        _check(rc, "mih_knn_approx")
+        out = _shape(ids, dists, total, nq, kk, kl)
+        return (*out, st.as_dict()) if stats else out
+
     def knn(self, queries: torch.Tensor, k, stats: bool = False):
         """Exact kNN; k is an int or a per-query sequence (then rows are flat)."""
         queries = _codes_arg(queries, "queries")
@@ -343,16 +369,53 @@ class Index:
 
 
 def build(codes: torch.Tensor, m: int, table_mode: str = "auto", codes_mode: str = "auto",
-          mem_budget_bytes: int = 0) -> Index:
-    """Build the m substring tables (Algorithm 1) on the device."""
+          mem_budget_bytes: int = 0, bit_order=None) -> Index:
+    """Build the m substring tables (Algorithm 1) on the device; bit_order
+    (a permutation of the code bits, Section 5.4) places the substrings."""
     codes = _codes_arg(codes, "codes")
     n, W = codes.shape
-    opts = BuildOpts(TABLE_MODES[table_mode], CODES_MODES[codes_mode], mem_budget_bytes)
+    order = None
+    if bit_order is not None:
+        if len(bit_order) != 64 * W:
+            raise ValueError("bit_order must list every code bit once")
+        order = (ctypes.c_uint16 * (64 * W))(*[int(b) for b in bit_order])
+    opts = BuildOpts(TABLE_MODES[table_mode], CODES_MODES[codes_mode], mem_budget_bytes,
+                     ctypes.cast(order, ctypes.c_void_p) if order is not None else None)
     h = ctypes.c_void_p()
     rc = load().mih_build(codes.data_ptr() if n else None, n, 64 * W, m, ctypes.byref(opts),
                           _stream(), ctypes.byref(h))
     _check(rc, "mih_build")
     return Index(h, codes)
+
+
+def bit_cooccurrence(codes: torch.Tensor):
+    """counts[i, j] = number of codes with bits i and j set (numpy uint32 [bits, bits])."""
+    import numpy as np
+    codes = _codes_arg(codes, "codes")
+    n, W = codes.shape
+    bits = 64 * W
+    out = np.zeros((bits, bits), dtype=np.uint32)
+    _check(load().mih_bit_cooccurrence(codes.data_ptr() if n else None, n, bits, _stream(),
+                                       out.ctypes.data), "mih_bit_cooccurrence")
+    return out
+
+
+def greedy_bit_order(counts, n: int, m: int, first_bit: int = 0):
+    """The Section 5.4 greedy bit order from co-occurrence counts of n codes."""
+    import numpy as np
+    counts = np.ascontiguousarray(counts, dtype=np.uint32)
+    bits = counts.shape[0]
+    order = np.zeros(bits, dtype=np.uint16)
+    _check(load().mih_greedy_bit_order(counts.ctypes.data, n, bits, m, first_bit, order.ctypes.data),
+           "mih_greedy_bit_order")
+    return order.tolist()
+
+
+def optimize_substrings(codes: torch.Tensor, m: int, sample: int = 1_000_000, first_bit: int = 0):
+    """Bit order for build(): counts over the first `sample` codes, then the greedy order."""
+    n = min(sample, codes.shape[0])
+    counts = bit_cooccurrence(codes[:n])
+    return greedy_bit_order(counts, n, m, first_bit)
 
 
 def model_cost(n: int, bits: int, m: int, r: int) -> float:

@@ -410,10 +410,12 @@ bool use_graphs()
 // Runs one request of nq queries through an engine until it completes.
 mih_status engine_batch(mih::Engine &eng, const uint64_t *queries, uint32_t nq,
                         const std::vector<uint32_t> &k, const std::vector<uint64_t> &row_off,
-                        uint32_t *out_ids, uint32_t *out_dists)
+                        uint32_t *out_ids, uint32_t *out_dists, uint32_t max_t = 0xFFFFFFFFu,
+                        uint32_t budget = 0)
 {
     std::vector<uint64_t> completed;
-    eng.submit(queries, nq, k.data(), row_off.data(), out_ids, out_dists);
+    eng.set_count_unique(budget != 0);
+    eng.submit(queries, nq, k.data(), row_off.data(), out_ids, out_dists, max_t, budget);
     uint64_t guard = 0;
     while (!eng.idle()) {
         MIH_TRY(eng.step(completed));
@@ -519,8 +521,16 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     if (!bits_ok(bits) || m < 1 || m > MIH_M_MAX || m > bits) return MIH_ERR_INVALID;
     if ((bits + m - 1) / m > MIH_SUBSTRING_MAX) return MIH_ERR_UNSUPPORTED;
     if (n > 0xFFFFFFFEull || (n && !codes) || ((uintptr_t)codes & 7) != 0) return MIH_ERR_INVALID;
-    mih_build_opts o = {MIH_TABLE_AUTO, MIH_CODES_AUTO, 0};
+    mih_build_opts o = {MIH_TABLE_AUTO, MIH_CODES_AUTO, 0, nullptr};
     if (opts) o = *opts;
+    if (o.bit_order) {
+        // a permutation of 0 .. bits-1
+        std::vector<uint8_t> seen(bits, 0);
+        for (uint32_t p = 0; p < bits; ++p) {
+            if (o.bit_order[p] >= bits || seen[o.bit_order[p]]) return MIH_ERR_INVALID;
+            seen[o.bit_order[p]] = 1;
+        }
+    }
     if (o.table_mode > MIH_TABLE_GROUPED || o.codes_mode > MIH_CODES_INDIRECT) return MIH_ERR_INVALID;
     // a GROUPED table finds a bucket by scanning the codes in table order
     if (o.table_mode == MIH_TABLE_GROUPED && o.codes_mode == MIH_CODES_INDIRECT) return MIH_ERR_INVALID;
@@ -538,6 +548,7 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     {
         uint32_t base = bits / m, extra = bits % m, st = 0;
         ix->t_all = 0xFFFFFFFFu;
+        for (uint32_t p = 0; p < bits; ++p) ix->bit_order[p] = o.bit_order ? o.bit_order[p] : (uint16_t)p;
         for (uint32_t j = 0; j < m; ++j) {
             ix->len[j] = base + (j < extra ? 1 : 0);
             ix->start[j] = st;
@@ -600,11 +611,21 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
             T.len = ix->len[j];
             T.start = ix->start[j];
             T.dir_bits = ix->dir_bits[j];
+            // the substring's bits: a mask for substring distances and, when
+            // they are not the consecutive run [start, start + len), the
+            // order in which they form the key
+            T.permuted = 0;
+            for (uint32_t k = 0; k < T.len; ++k) {
+                const uint32_t b = ix->bit_order[T.start + k];
+                T.mask[b >> 6] |= 1ull << (b & 63);
+                T.order[k] = (uint8_t)b;
+                if (b != T.start + k) T.permuted = 1;
+            }
             uint32_t *ids = nullptr;
             if ((e = ix->alloc((void **)&ids, n * 4)) != hipSuccess) { st = from_hip(e); break; }
             uint32_t *keys = (uint32_t *)tk1.ptr, *keys2 = (uint32_t *)tk2.ptr, *ids2 = (uint32_t *)ti2.ptr;
             uint32_t *ids_cur = ids;
-            e = mih::extract_keys(codes, n, W, T.start, T.len, keys, ids_cur, s);
+            e = mih::extract_keys(codes, n, W, T, keys, ids_cur, s);
             if (e == hipSuccess)
                 e = mih::radix_sort_pairs(keys, ids_cur, keys2, ids2, n, T.len, (uint32_t *)tmp.ptr, s);
             if (e == hipSuccess && ids_cur != ids)
@@ -669,9 +690,38 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     return MIH_OK;
 }
 
+namespace {
+
+// kNN through the index's batch engine, exact or stopped early.
+mih_status knn_common(const mih_index *cidx, const uint64_t *queries, uint32_t nq, uint32_t k,
+                      const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
+                      void *stream, mih_query_stats *stats, uint32_t max_t, uint32_t budget);
+
+}  // namespace
+
 mih_status mih_knn_ex(const mih_index *cidx, const uint64_t *queries, uint32_t nq, uint32_t k,
                       const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
                       void *stream, mih_query_stats *stats)
+{
+    return knn_common(cidx, queries, nq, k, k_per_query, out_ids, out_dists, stream, stats,
+                      0xFFFFFFFFu, 0);
+}
+
+mih_status mih_knn_approx(const mih_index *cidx, const uint64_t *queries, uint32_t nq, uint32_t k,
+                          const uint32_t *k_per_query, uint32_t max_radius, uint32_t max_candidates,
+                          uint32_t *out_ids, uint32_t *out_dists, void *stream, mih_query_stats *stats)
+{
+    return knn_common(cidx, queries, nq, k, k_per_query, out_ids, out_dists, stream, stats,
+                      max_radius, max_candidates);
+}
+
+}  // extern "C"
+
+namespace {
+
+mih_status knn_common(const mih_index *cidx, const uint64_t *queries, uint32_t nq, uint32_t k,
+                      const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
+                      void *stream, mih_query_stats *stats, uint32_t max_t, uint32_t budget)
 {
     auto t0 = clk::now();
     if (!cidx) return MIH_ERR_INVALID;
@@ -702,7 +752,7 @@ mih_status mih_knn_ex(const mih_index *cidx, const uint64_t *queries, uint32_t n
     mih::Engine &eng = *ix->batch_engine;
     eng.set_stream(s);
     MIH_TRY(eng.reset_stats());
-    mih_status st = engine_batch(eng, queries, nq, kv, row_off, out_ids, out_dists);
+    mih_status st = engine_batch(eng, queries, nq, kv, row_off, out_ids, out_dists, max_t, budget);
     if (st != MIH_OK) { ix->batch_engine.reset(); return st; }
     if (stats) {
         mih::EngineStats es;
@@ -711,6 +761,10 @@ mih_status mih_knn_ex(const mih_index *cidx, const uint64_t *queries, uint32_t n
     }
     return MIH_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 mih_status mih_knn(const mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
                    const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists, void *stream)
@@ -751,6 +805,7 @@ mih_status mih_rnn_ex(const mih_index *cidx, const uint64_t *queries, uint32_t n
     mih::Engine &eng = *ix->batch_engine;
     eng.set_stream(s);
     MIH_TRY(eng.reset_stats());
+    eng.set_count_unique(false);
     const uint64_t ticket = eng.submit_rnn(queries, nq, rv.data());
     std::vector<uint64_t> completed;
     uint64_t guard = 0;
@@ -844,6 +899,7 @@ mih_status mih_index_get_info(const mih_index *idx, mih_index_info *info)
     }
     info->device_bytes = idx->device_bytes;
     info->build_ms = idx->build_ms;
+    for (uint32_t p = 0; p < idx->bits; ++p) info->bit_order[p] = idx->bit_order[p];
     return MIH_OK;
 }
 

@@ -16,8 +16,7 @@ constexpr uint32_t kTile = MIH_BLOCK * kItems;
 
 template <int W>
 __global__ __launch_bounds__(MIH_BLOCK) void extract_keys_kernel(const uint64_t *__restrict__ codes,
-                                                                 uint64_t n, uint32_t start,
-                                                                 uint32_t len, uint32_t *keys,
+                                                                 uint64_t n, TableDev T, uint32_t *keys,
                                                                  uint32_t *ids)
 {
     uint64_t i = (uint64_t)blockIdx.x * MIH_BLOCK + threadIdx.x;
@@ -25,7 +24,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void extract_keys_kernel(const uint64_t 
     for (; i < n; i += stride) {
         uint64_t c[W];
         load_code<W>(codes + i * W, c);
-        keys[i] = substring<W>(c, start, len);
+        keys[i] = table_key<W>(c, T);
         ids[i] = (uint32_t)i;
     }
 }
@@ -179,16 +178,16 @@ uint32_t grid_for(uint64_t n)
 
 namespace mih {
 
-hipError_t extract_keys(const uint64_t *codes, uint64_t n, uint32_t W, uint32_t start,
-                        uint32_t len, uint32_t *keys, uint32_t *ids, hipStream_t s)
+hipError_t extract_keys(const uint64_t *codes, uint64_t n, uint32_t W, const TableDev &T,
+                        uint32_t *keys, uint32_t *ids, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const uint32_t g = grid_for(n);
     switch (W) {
-    case 1: extract_keys_kernel<1><<<g, MIH_BLOCK, 0, s>>>(codes, n, start, len, keys, ids); break;
-    case 2: extract_keys_kernel<2><<<g, MIH_BLOCK, 0, s>>>(codes, n, start, len, keys, ids); break;
-    case 3: extract_keys_kernel<3><<<g, MIH_BLOCK, 0, s>>>(codes, n, start, len, keys, ids); break;
-    case 4: extract_keys_kernel<4><<<g, MIH_BLOCK, 0, s>>>(codes, n, start, len, keys, ids); break;
+    case 1: extract_keys_kernel<1><<<g, MIH_BLOCK, 0, s>>>(codes, n, T, keys, ids); break;
+    case 2: extract_keys_kernel<2><<<g, MIH_BLOCK, 0, s>>>(codes, n, T, keys, ids); break;
+    case 3: extract_keys_kernel<3><<<g, MIH_BLOCK, 0, s>>>(codes, n, T, keys, ids); break;
+    case 4: extract_keys_kernel<4><<<g, MIH_BLOCK, 0, s>>>(codes, n, T, keys, ids); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -51,6 +51,7 @@ struct mih_index {
     uint32_t bits = 0, W = 0, m = 0;
     uint32_t table_mode = 0, codes_mode = 0;
     uint32_t len[MIH_M_MAX] = {}, start[MIH_M_MAX] = {}, dir_bits[MIH_M_MAX] = {};
+    uint16_t bit_order[256] = {};
     uint32_t t_all = 0;
     TableDev tables_host[MIH_M_MAX] = {};
     TableDev *tables_dev = nullptr;
@@ -90,8 +91,15 @@ public:
 
     // A request of nq queries with per-query k (host), output rows at
     // row_off[i] in out_ids / out_dists (device).  Returns its ticket.
+    // An approximate request (Section 7) stops each query after step max_t
+    // or once `budget` distinct codes were met (budget 0: no limit); counting
+    // distinct codes must be switched on first (set_count_unique).
     uint64_t submit(const uint64_t *queries, uint32_t nq, const uint32_t *k,
-                    const uint64_t *row_off, uint32_t *out_ids, uint32_t *out_dists);
+                    const uint64_t *row_off, uint32_t *out_ids, uint32_t *out_dists,
+                    uint32_t max_t = 0xFFFFFFFFu, uint32_t budget = 0);
+    // Count distinct codes per query (needed by budgets; off by default).
+    // Only while the engine is idle.
+    void set_count_unique(bool on) { count_unique_ = on; }
     // A request of nq r-neighbour queries with per-query radius (host).  Its
     // results are taken with take_rnn() once the ticket has completed.
     uint64_t submit_rnn(const uint64_t *queries, uint32_t nq, const uint32_t *radius);
@@ -117,6 +125,7 @@ private:
         uint32_t *out_ids, *out_dists;
         uint32_t next = 0, done = 0;
         std::vector<uint32_t> radius;            // r-neighbour requests only
+        uint32_t max_t = 0xFFFFFFFFu, budget = 0;  // approximate requests
         std::unique_ptr<RnnCollector> rnn;       // non-null for r-neighbour requests
     };
     struct SlotInfo {
@@ -147,6 +156,8 @@ private:
     uint32_t *new_slots_ = nullptr, *done_list_ = nullptr, *ovf_list_ = nullptr;
     uint32_t *bound_tau_ = nullptr, *bound_cap_ = nullptr;
     uint32_t *tmp_list_ = nullptr, *tmp_cnt_ = nullptr;
+    uint32_t *max_t_ = nullptr, *budget_ = nullptr, *uniq_ = nullptr;
+    bool count_unique_ = false, graph_count_unique_ = false;
     uint64_t *out_ids_ = nullptr, *out_dists_ = nullptr;
     Group *groups_ = nullptr;
     Control *ctrl_ = nullptr;

@@ -121,7 +121,8 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
                    o_ovf = take(4ull * S_), o_btau = take(4ull * S_), o_bcap = take(4ull * S_),
                    o_grp = take(sizeof(Group) * (ix_->t_all + 1)), o_ctrl = take(sizeof(Control)),
                    o_work = take(8 * (1 + kSweepXcds)), o_stats = take(8 * 4), o_adm = take(sizeof(AdmitRec) * S_),
-                   o_tl = take(4ull * S_), o_tc = take(4ull * S_);
+                   o_tl = take(4ull * S_), o_tc = take(4ull * S_), o_mt = take(4ull * S_),
+                   o_bg = take(4ull * S_), o_uq = take(4ull * S_);
     hipError_t e = hipMalloc(&dev_, used);
     if (e != hipSuccess) { dev_ = nullptr; return e; }
     char *b = (char *)dev_;
@@ -152,6 +153,9 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
     admit_dev_ = (AdmitRec *)(b + o_adm);
     tmp_list_ = (uint32_t *)(b + o_tl);
     tmp_cnt_ = (uint32_t *)(b + o_tc);
+    max_t_ = (uint32_t *)(b + o_mt);
+    budget_ = (uint32_t *)(b + o_bg);
+    uniq_ = (uint32_t *)(b + o_uq);
 
     const uint64_t pe = pool_entries ? pool_entries : 1;
     e = hipMalloc((void **)&pool_mem_, pe * 8);
@@ -188,7 +192,12 @@ void Engine::fill_args(MihArgs &A) const
     A.chunk = ix_->tuning.chunk;
     A.J = ix_->tuning.probes_per_lane;
     A.occ_filter = ix_->tuning.occupancy_filter && ix_->table_mode == MIH_TABLE_DIRECT;
-    A.sweep_shift = ix_->tuning.sweep_shift;
+    // distinct codes are counted in whole-step probing only
+    A.sweep_shift = count_unique_ ? 0u : ix_->tuning.sweep_shift;
+    A.count_unique = count_unique_ ? 1u : 0u;
+    A.max_t = max_t_;
+    A.budget = budget_;
+    A.uniq = uniq_;
     A.sweep_bits = ix_->tuning.sweep_bits;
     A.qb = qb_;
     A.t = t_;
@@ -208,7 +217,8 @@ void Engine::fill_args(MihArgs &A) const
 }
 
 uint64_t Engine::submit(const uint64_t *queries, uint32_t nq, const uint32_t *k,
-                        const uint64_t *row_off, uint32_t *out_ids, uint32_t *out_dists)
+                        const uint64_t *row_off, uint32_t *out_ids, uint32_t *out_dists,
+                        uint32_t max_t, uint32_t budget)
 {
     const uint64_t ticket = next_ticket_++;
     Req r;
@@ -218,6 +228,8 @@ uint64_t Engine::submit(const uint64_t *queries, uint32_t nq, const uint32_t *k,
     r.row_off.assign(row_off, row_off + nq);
     r.out_ids = out_ids;
     r.out_dists = out_dists;
+    r.max_t = max_t;
+    r.budget = budget;
     reqs_.emplace(ticket, std::move(r));
     pending_.push_back(ticket);
     return ticket;
@@ -289,6 +301,8 @@ hipError_t Engine::admit()
         a.k = r.k[si.query];
         a.cap = rr.cap;
         a.tau0 = rr.tau0;
+        a.max_t = r.max_t;
+        a.budget = r.budget;
         a.buf_off = off;
         a.query = (uint64_t)(uintptr_t)(qb_.queries + (uint64_t)rr.slot * W);
         a.out_ids = r.rnn ? 0 : (uint64_t)(uintptr_t)(r.out_ids + r.row_off[si.query]);
@@ -318,6 +332,8 @@ hipError_t Engine::admit()
             a.slot = slot;
             a.k = k;
             a.cap = cap;
+            a.max_t = r.max_t;
+            a.budget = r.budget;
             // an r-neighbour query starts (and stays) at its radius
             a.tau0 = r.rnn ? std::min(r.radius[i], ix_->bits) : ix_->bits;
             a.buf_off = off;
@@ -355,6 +371,7 @@ hipError_t Engine::capture_graph()
     sweep_grid_ = cu_count() * per_cu_sweep;
     if (!use_graph_) {
         graph_tuning_version_ = ix_->tuning_version;
+        graph_count_unique_ = count_unique_;
         return hipSuccess;
     }
     hipStream_t cs = nullptr;
@@ -381,13 +398,15 @@ hipError_t Engine::capture_graph()
         use_graph_ = false;
     }
     graph_tuning_version_ = ix_->tuning_version;
+    graph_count_unique_ = count_unique_;
     return hipSuccess;
 }
 
 hipError_t Engine::run_round()
 {
     hipError_t e;
-    if (graph_tuning_version_ != ix_->tuning_version || (use_graph_ && !graph_exec_)) {
+    if (graph_tuning_version_ != ix_->tuning_version || (use_graph_ && !graph_exec_) ||
+        graph_count_unique_ != count_unique_) {
         if ((e = capture_graph()) != hipSuccess) return e;
     }
     if (use_graph_ && graph_exec_) {

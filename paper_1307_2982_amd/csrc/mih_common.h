@@ -209,6 +209,10 @@ struct RnnMove {
 // ----------------------------------------------------------- index layout
 
 struct TableDev {
+    uint64_t mask[4];        // the code bits of this substring (words 0..W-1)
+    uint8_t order[32];       // permuted: key bit k is code bit order[k]
+    uint32_t permuted;       // 0: key bits are code bits [start, start + len)
+    uint32_t pad0;
     const uint32_t *off;     // DIRECT: [2^len + 1]
     const uint32_t *occ;     // DIRECT: [2^len / 32 (at least 1)] bit v: bucket v non-empty
     const uint64_t *grp;     // GROUPED: [2^len / 32 (at least 1)]: bits 0..31 occupancy of
@@ -219,6 +223,42 @@ struct TableDev {
     const uint64_t *codes;   // INLINE: [n][W]
     uint32_t len, start, dir_bits, pad;
 };
+
+// Word idx of a code held in registers (W <= 4, idx < W).
+template <int W>
+__device__ __forceinline__ uint64_t code_word(const uint64_t (&c)[W], uint32_t idx)
+{
+    uint64_t v = c[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w)
+        if ((uint32_t)w == idx) v = c[w];
+    return v;
+}
+
+// Key of a code in table T: its substring bits, contiguous or in the table's
+// bit order (substring optimisation, Section 5.4).
+template <int W>
+__device__ __forceinline__ uint32_t table_key(const uint64_t (&c)[W], const TableDev &T)
+{
+    if (!T.permuted) return substring<W>(c, T.start, T.len);
+    uint32_t key = 0;
+    for (uint32_t k = 0; k < T.len; ++k) {
+        const uint32_t b = T.order[k];
+        key |= (uint32_t)((code_word<W>(c, b >> 6) >> (b & 63)) & 1u) << k;
+    }
+    return key;
+}
+
+// Hamming distance of two codes restricted to table T's substring, from
+// their xor.
+template <int W>
+__device__ __forceinline__ uint32_t table_dist(const uint64_t (&x)[W], const TableDev &T)
+{
+    uint32_t d = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) d += __popcll(x[w] & T.mask[w]);
+    return d;
+}
 
 // ----------------------------------------------------------- host wrappers
 
@@ -240,8 +280,9 @@ hipError_t gather_rows(const uint64_t *rows, const uint32_t *list, uint32_t nlis
                        uint64_t *dst, hipStream_t s);
 
 // build.hip
-hipError_t extract_keys(const uint64_t *codes, uint64_t n, uint32_t W, uint32_t start,
-                        uint32_t len, uint32_t *keys, uint32_t *ids, hipStream_t s);
+// keys[i] = key of code i in table T (T's bit layout fields only), ids[i] = i.
+hipError_t extract_keys(const uint64_t *codes, uint64_t n, uint32_t W, const TableDev &T,
+                        uint32_t *keys, uint32_t *ids, hipStream_t s);
 uint64_t radix_tmp_words(uint64_t n);
 // Stable sort of (keys, ids) by the low `key_bits` bits of keys, ping-ponging
 // between (keys, ids) and (keys2, ids2); on return (keys, ids) name the

@@ -47,6 +47,8 @@ struct Control {
 // One admitted query: its slot and the state it starts from.
 struct AdmitRec {
     uint32_t slot, k, cap, tau0;
+    uint32_t max_t;       // stop after this step at the latest (~0: no limit)
+    uint32_t budget;      // stop once this many distinct codes were met (0: no limit)
     uint64_t buf_off;     // first buffer entry of the slot
     uint64_t query;       // device address of the query's words
     uint64_t out_ids;     // device address of the query's output row
@@ -68,6 +70,10 @@ struct MihArgs {
     uint32_t sweep_bits;      // key bits enumerated inside one sweep partition
     QueryBatch qb;            // per-slot state (qb.queries is slot storage)
     uint32_t *t;              // [slots] current step of each query
+    uint32_t *max_t;          // [slots] last step allowed (approximate search), or ~0
+    uint32_t *budget;         // [slots] distinct codes after which to stop, or 0
+    uint32_t *uniq;           // [slots] distinct codes met so far (when count_unique)
+    uint32_t count_unique;    // some admitted query has a budget: count distinct codes
     uint64_t *out_ids;        // [slots] output row of each query
     uint64_t *out_dists;      // [slots]
     uint32_t *active;         // [slots] active list, grouped by step

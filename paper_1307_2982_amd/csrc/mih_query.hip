@@ -79,17 +79,23 @@ struct WaveStats {
     uint64_t probes, candidates;
 };
 
-// Substring value of the code at table position pos (INLINE codes): only
-// the one or two words that hold bits [start, start + len) are read.
+// Key of the code at table position pos (INLINE codes).  With contiguous
+// substrings only the one or two words that hold bits [start, start + len)
+// are read.
 template <int W>
-__device__ __forceinline__ uint32_t entry_key(const uint64_t *codes, uint64_t pos, uint32_t start,
-                                              uint32_t len)
+__device__ __forceinline__ uint32_t entry_key(const TableDev &T, uint64_t pos)
 {
-    const uint32_t w = start >> 6, o = start & 63;
-    const uint64_t *c = codes + pos * W + w;
-    uint64_t v = c[0] >> o;
-    if (o + len > 64) v |= c[1] << (64 - o);
-    return (uint32_t)(v & ((len >= 32) ? 0xFFFFFFFFull : ((1ull << len) - 1)));
+    const uint64_t *c = T.codes + pos * W;
+    if (T.permuted) {
+        uint64_t g[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) g[w] = c[w];
+        return table_key<W>(g, T);
+    }
+    const uint32_t w = T.start >> 6, o = T.start & 63;
+    uint64_t v = c[w] >> o;
+    if (o + T.len > 64) v |= c[w + 1] << (64 - o);
+    return (uint32_t)(v & ((T.len >= 32) ? 0xFFFFFFFFull : ((1ull << T.len) - 1)));
 }
 
 // First position in [p, n) whose substring value is at least `key`, given
@@ -100,14 +106,14 @@ __device__ __forceinline__ uint32_t gallop_at_least(const TableDev &T, uint64_t 
                                                     uint32_t p)
 {
     uint64_t lo = p, step = 1;
-    while (lo + step <= n && entry_key<W>(T.codes, lo + step - 1, T.start, T.len) < key) {
+    while (lo + step <= n && entry_key<W>(T, lo + step - 1) < key) {
         lo += step;
         step <<= 1;
     }
     uint64_t hi = lo + step < n ? lo + step : n;   // the answer lies in [lo, hi]
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
-        if (entry_key<W>(T.codes, mid, T.start, T.len) < key) lo = mid + 1; else hi = mid;
+        if (entry_key<W>(T, mid) < key) lo = mid + 1; else hi = mid;
     }
     return (uint32_t)lo;
 }
@@ -126,7 +132,7 @@ __device__ __forceinline__ void group_scan(const TableDev &T, uint64_t n, uint32
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint64_t pos = (uint64_t)p + i;
-        const uint64_t v = pos < n ? (uint64_t)entry_key<W>(T.codes, pos, T.start, T.len) : (1ull << 32);
+        const uint64_t v = pos < n ? (uint64_t)entry_key<W>(T, pos) : (1ull << 32);
         lt += v < key ? 1u : 0u;
         eq += v == key ? 1u : 0u;
     }
@@ -150,7 +156,7 @@ __device__ __forceinline__ uint32_t query_key(const mih::MihArgs &A, uint32_t q,
 {
 #pragma unroll
     for (int w = 0; w < W; ++w) g[w] = u64_uniform<W>(A.qb.queries[(uint64_t)q * W + w]);
-    return substring<W>(g, A.tables[a].start, A.tables[a].len);
+    return table_key<W>(g, A.tables[a]);
 }
 
 // Part of step t of query q: the buckets key_base ^ mask for the masks of
@@ -286,18 +292,25 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
                 for (int w = 0; w < W; ++w) code[w] = g[w];
             }
             const uint32_t d = hamming<W>(code, g);
-            bool keep = live && d <= tau;
-            if (keep) {
+            // first encounter of the code (row a8); every candidate is tested
+            // when distinct codes are counted, else only those within tau
+            bool first = live && (A.count_unique || d <= tau);
+            if (first) {
                 uint64_t x[W];
 #pragma unroll
                 for (int w = 0; w < W; ++w) x[w] = code[w] ^ g[w];
                 for (uint32_t j = 0; j < m; ++j) {
                     if (j == a) continue;
-                    const uint32_t dj = __popc(substring<W>(x, A.tables[j].start, A.tables[j].len));
-                    if (j < a ? dj <= rp : dj < rp) { keep = false; break; }
+                    const uint32_t dj = table_dist<W>(x, A.tables[j]);
+                    if (j < a ? dj <= rp : dj < rp) { first = false; break; }
                 }
-                if (keep && INLINE) id = T.ids[pos];
             }
+            if (A.count_unique) {
+                const uint64_t fb = __ballot(first);
+                if (fb && lane == 0) atomicAdd(A.uniq + q, (uint32_t)__popcll(fb));
+            }
+            const bool keep = first && d <= tau;
+            if (keep && INLINE) id = T.ids[pos];
             append_candidates(A.qb, q, keep, d, id);
             if (__ballot(keep)) tau = tighten_tau(A.qb, q, tau);
         }
@@ -351,7 +364,8 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
         // the whole step belonged to this wave: keep going while steps are small
         for (;;) {
             const uint32_t tau = tighten_tau(A.qb, q, __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q)));
-            if (tau <= t || t >= A.t_all) break;
+            if (tau <= t || t >= A.t_all || t >= A.max_t[q]) break;
+            if (A.budget[q] && __builtin_amdgcn_readfirstlane(load_relaxed(A.uniq + q)) >= A.budget[q]) break;
             const uint32_t tn = t + 1;
             const uint32_t rpn = tn / A.m;
             const uint32_t Mn = binom_calc(A.tables[tn - rpn * A.m].len, rpn);
@@ -478,7 +492,7 @@ __device__ void sweep_item(const mih::MihArgs &A, const mih::Group &G, uint32_t 
         uint64_t g[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) g[w] = A.qb.queries[(uint64_t)q * W + w];
-        const uint32_t key = substring<W>(g, T.start, T.len);
+        const uint32_t key = table_key<W>(g, T);
         const uint32_t wgt = __popc((L >= 32 ? 0u : key >> L) ^ h);
         const uint32_t rho = wgt <= rp ? rp - wgt : 0xFFFFFFFFu;
         M = rho <= L ? binom[L][rho] : 0u;
@@ -589,7 +603,7 @@ __device__ void sweep_item(const mih::MihArgs &A, const mih::Group &G, uint32_t 
                     for (int w = 0; w < W; ++w) x[w] = code[w] ^ g[w];
                     for (uint32_t j = 0; j < A.m; ++j) {
                         if (j == a) continue;
-                        const uint32_t dj = __popc(substring<W>(x, A.tables[j].start, A.tables[j].len));
+                        const uint32_t dj = table_dist<W>(x, A.tables[j]);
                         if (j < a ? dj <= rp : dj < rp) { keep = false; break; }
                     }
                 }
@@ -692,9 +706,12 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
     if (D < tau) { A.qb.tau[q] = D; tau = D; }
     uint32_t t = A.t[q];
     uint32_t out = 0xFFFFFFFFu;
-    // after step t every code within distance t has been found (Prop. 2)
-    if (!(tau <= t || t >= A.t_all)) {
-        for (uint32_t tn = t + 1;; ++tn) {
+    // after step t every code within distance t has been found (Prop. 2);
+    // an approximate query also stops at its step limit or candidate budget
+    const uint32_t max_t = A.max_t[q], budget = A.budget[q];
+    const bool spent = budget != 0 && A.uniq[q] >= budget;
+    if (!(tau <= t || t >= A.t_all || t >= max_t || spent)) {
+        for (uint32_t tn = t + 1; tn <= max_t; ++tn) {
             const uint32_t rp = tn / A.m;
             if (binom_calc(A.tables[tn - rp * A.m].len, rp) > 0) { out = tn; break; }
             if (tau <= tn || tn >= A.t_all) break;
@@ -815,6 +832,9 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_admit_kernel(mih::MihArgs A, co
     A.qb.tau[q] = r.tau0;
     A.qb.count[q] = 0;
     A.t[q] = 0;
+    A.max_t[q] = r.max_t;
+    A.budget[q] = r.budget;
+    A.uniq[q] = 0;
     A.out_ids[q] = r.out_ids;
     A.out_dists[q] = r.out_dists;
     uint32_t *h = A.qb.hist + (uint64_t)q * (A.bits + 1);
