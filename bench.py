@@ -196,18 +196,34 @@ def serve_bench(mih, idx, kind, bits, k_choices, args, log_fn):
         arrivals = arrivals - arrivals[0]
         lat, end, st, same = run(arrivals)
         body = lat[warm:]
+        wsz = sizes[warm:]
         qps = total / end
+        # per query: a query's results are ready when its request completes
         rec = {"load": load, "rate_req_per_s": round(rate, 2), "p50_ms": round(pct(body, 50), 2),
                "p99_ms": round(pct(body, 99), 2), "mean_ms": round(float(body.mean()), 2),
+               "per_query_p50_ms": round(weighted_pct(body, wsz, 50), 2),
+               "per_query_p99_ms": round(weighted_pct(body, wsz, 99), 2),
                "qps": round(qps, 1), "rounds": st["rounds"], "same_as_alone": same}
         out["loads"].append(rec)
         log_fn(f"serving at {load:.0%} load ({rate:.1f} req/s): p50 {rec['p50_ms']} ms, "
-               f"p99 {rec['p99_ms']} ms, {qps:,.0f} queries/s, mix == alone: {same}")
+               f"p99 {rec['p99_ms']} ms (per query {rec['per_query_p50_ms']} / {rec['per_query_p99_ms']} ms), "
+               f"{qps:,.0f} queries/s, mix == alone: {same}")
     return out
 
 
 def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
+
+
+def weighted_pct(a, w, q):
+    """Percentile of values a with integer weights w (each request counted
+    once per query it carries)."""
+    if not len(a):
+        return None
+    order = np.argsort(a, kind="stable")
+    cw = np.cumsum(np.asarray(w, dtype=np.float64)[order])
+    i = int(np.searchsorted(cw, q / 100.0 * cw[-1], side="left"))
+    return float(np.asarray(a)[order][min(i, len(a) - 1)])
 
 
 def main():

@@ -178,7 +178,6 @@ private:
     std::unordered_map<uint64_t, RnnOut> rnn_out_;   // finished r-neighbour requests
     uint64_t next_ticket_ = 1;
     uint32_t in_flight_ = 0;       // admitted queries not yet finished
-    bool ctrl_has_active_ = false;
     EngineStats stats_host_;
 };
 
