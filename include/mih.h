@@ -301,7 +301,7 @@ mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
 mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning);
 
 /* Time mih_knn over a grid of tunings (probes_per_lane 4, 8, 16; chunk of
- * 8, 32 or 128 times 64 * probes_per_lane; all workgroups that fit; with and
+ * 2, 8, 32 or 128 times 64 * probes_per_lane; all workgroups that fit; with and
  * without the occupancy filter on DIRECT tables; and, for substrings of 20
  * bits or more, sweeps with sweep_shift 3 and 18 or 20 sweep bits) on the
  * given sample of queries, keep the fastest in the index and write it to

@@ -1072,7 +1072,7 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
     const uint32_t filters = idx->table_mode == MIH_TABLE_DIRECT ? 2 : 1;
     for (uint32_t f = 0; f < filters; ++f)
         for (uint32_t J : {4u, 8u, 16u})
-            for (uint32_t mult : {8u, 32u, 128u}) {
+            for (uint32_t mult : {2u, 8u, 32u, 128u}) {
                 mih_tuning t = idx->tuning;
                 t.probes_per_lane = J;
                 t.chunk = 64 * J * mult;

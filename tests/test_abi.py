@@ -56,3 +56,15 @@ def test_argument_errors_need_no_device():
     assert lib.linscan_rnn(None, 0, 64, None, 0, 3, None, None, None) == 1        # out NULL
     assert lib.mih_rnn_result_view(None, None) == 1
     lib.mih_rnn_result_free(None)                                                 # ignored
+
+
+def test_header_is_plain_c():
+    # the boundary compiles as C99 (no C++ or HIP types leak into it)
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", HEADER],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
