@@ -140,6 +140,7 @@ private:
     hipError_t admit();
     hipError_t run_round();
     hipError_t collect_rnn(const std::vector<uint32_t> &slots);
+    hipError_t finish_round(const MihArgs &A, hipStream_t s);
     hipError_t complete(uint64_t ticket, Req &r, std::vector<uint64_t> &completed);
     hipError_t capture_graph();
     void fill_args(MihArgs &A) const;
@@ -164,6 +165,7 @@ private:
     unsigned long long *work_ = nullptr, *stats_ = nullptr;
     AdmitRec *admit_dev_ = nullptr;
     Control *ctrl_host_ = nullptr;   // pinned
+    uint32_t *done_host_ = nullptr;  // pinned [slots]: the last round's done list
     hipEvent_t ev_a_ = nullptr, ev_b_ = nullptr;
     hipGraph_t graph_ = nullptr;
     hipGraphExec_t graph_exec_ = nullptr;

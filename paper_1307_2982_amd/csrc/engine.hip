@@ -101,6 +101,7 @@ Engine::~Engine()
     if (ev_a_) (void)hipEventDestroy(ev_a_);
     if (ev_b_) (void)hipEventDestroy(ev_b_);
     if (ctrl_host_) (void)hipHostFree(ctrl_host_);
+    if (done_host_) (void)hipHostFree(done_host_);
     if (pool_mem_) (void)hipFree(pool_mem_);
     if (dev_) (void)hipFree(dev_);
     for (auto &kv : rnn_out_) free_rnn_out(kv.second);
@@ -165,6 +166,8 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
     e = hipHostMalloc((void **)&ctrl_host_, sizeof(Control), 0);
     if (e != hipSuccess) { ctrl_host_ = nullptr; return e; }
     std::memset(ctrl_host_, 0, sizeof(Control));
+    e = hipHostMalloc((void **)&done_host_, 4ull * S_, 0);
+    if (e != hipSuccess) { done_host_ = nullptr; return e; }
     if ((e = hipEventCreate(&ev_a_)) != hipSuccess || (e = hipEventCreate(&ev_b_)) != hipSuccess) return e;
     // zeroed control block, counters and statistics
     if ((e = fill_u32((uint32_t *)ctrl_, sizeof(Control) / 4, 0u, s_)) != hipSuccess) return e;
@@ -383,8 +386,7 @@ hipError_t Engine::capture_graph()
         if (e1 == hipSuccess && A.sweep_shift) e1 = mih_sweep(A, sweep_grid_, cs);
         if (e1 == hipSuccess) e1 = mih_round(A, round_grid_, cs);
         if (e1 == hipSuccess) e1 = mih_advance(A, S_, cs);
-        if (e1 == hipSuccess)
-            e1 = hipMemcpyAsync(ctrl_host_, ctrl_, sizeof(Control), hipMemcpyDeviceToHost, cs);
+        if (e1 == hipSuccess) e1 = finish_round(A, cs);
         e = hipStreamEndCapture(cs, &graph_);
         if (e1 != hipSuccess) e = e1;
     }
@@ -400,6 +402,18 @@ hipError_t Engine::capture_graph()
     graph_tuning_version_ = ix_->tuning_version;
     graph_count_unique_ = count_unique_;
     return hipSuccess;
+}
+
+// End of a round, on the device: the top-k rows of the finished queries,
+// then the control block and the done list to pinned host memory.
+hipError_t Engine::finish_round(const MihArgs &A, hipStream_t s)
+{
+    const uint32_t grid = std::min<uint32_t>(S_, cu_count() * 4);
+    hipError_t e = finalize_done(qb_, done_list_, &ctrl_->n_done, out_ids_, out_dists_, grid, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctrl_host_, ctrl_, sizeof(Control), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(done_host_, done_list_, 4ull * S_, hipMemcpyDeviceToHost, s);
+    (void)A;
+    return e;
 }
 
 hipError_t Engine::run_round()
@@ -424,8 +438,7 @@ hipError_t Engine::run_round()
         if ((e = mih_round(A, round_grid_, s_)) != hipSuccess) return e;
         if ((e = hipEventRecord(ev_b_, s_)) != hipSuccess) return e;
         if ((e = mih_advance(A, S_, s_)) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(ctrl_host_, ctrl_, sizeof(Control), hipMemcpyDeviceToHost, s_)) != hipSuccess)
-            return e;
+        if ((e = finish_round(A, s_)) != hipSuccess) return e;
     }
     if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
     float ms = 0;
@@ -452,28 +465,17 @@ hipError_t Engine::step(std::vector<uint64_t> &completed)
     }
     if (in_flight_ == 0) return hipSuccess;
     if ((e = run_round()) != hipSuccess) return e;
+    // the round already wrote the top-k rows of its finished kNN queries and
+    // copied the done list; r-neighbour hits are collected here
     const uint32_t n_done = ctrl_host_->n_done, n_ovf = ctrl_host_->n_ovf;
-    std::vector<uint32_t> done(n_done), ovf(n_ovf);
+    std::vector<uint32_t> done(done_host_, done_host_ + n_done), ovf(n_ovf);
     if (n_done) {
-        if ((e = sync_copy(done.data(), done_list_, 4ull * n_done, hipMemcpyDeviceToHost, s_)) != hipSuccess)
-            return e;
-        std::vector<uint32_t> knn, rnn;
+        std::vector<uint32_t> rnn;
         for (uint32_t q : done) {
             auto it = reqs_.find(slot_info_[q].ticket);
-            (it != reqs_.end() && it->second.rnn ? rnn : knn).push_back(q);
+            if (it != reqs_.end() && it->second.rnn) rnn.push_back(q);
         }
         if (!rnn.empty() && (e = collect_rnn(rnn)) != hipSuccess) return e;
-        if (!knn.empty()) {
-            const uint32_t *list = done_list_;
-            if (knn.size() != n_done) {
-                if ((e = sync_copy(tmp_list_, knn.data(), 4ull * knn.size(), hipMemcpyHostToDevice, s_)) !=
-                    hipSuccess)
-                    return e;
-                list = tmp_list_;
-            }
-            if ((e = finalize_list(qb_, list, (uint32_t)knn.size(), out_ids_, out_dists_, s_)) != hipSuccess)
-                return e;
-        }
     }
     if (n_ovf) {
         if ((e = sync_copy(ovf.data(), ovf_list_, 4ull * n_ovf, hipMemcpyDeviceToHost, s_)) != hipSuccess)

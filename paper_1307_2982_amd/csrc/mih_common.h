@@ -329,6 +329,11 @@ hipError_t finalize_topk(const FinalArgs &a, hipStream_t s);
 // addresses of query q's output rows.
 hipError_t finalize_list(const QueryBatch &qb, const uint32_t *list, uint32_t nlist,
                          const uint64_t *out_ids, const uint64_t *out_dists, hipStream_t s);
+// Top-k rows of the first *count queries of list (count in device memory),
+// skipping r-neighbour queries; grid workgroups share them.
+hipError_t finalize_done(const QueryBatch &qb, const uint32_t *list, const uint32_t *count,
+                         const uint64_t *out_ids, const uint64_t *out_dists, uint32_t grid,
+                         hipStream_t s);
 // For re-runs: per listed query, exact tau and the capacity it needs.
 hipError_t exact_bounds(const QueryBatch &qb, const uint32_t *list, uint32_t nlist,
                         uint32_t *tau_out, uint32_t *cap_out, hipStream_t s);

@@ -122,6 +122,24 @@ __global__ __launch_bounds__(MIH_BLOCK) void finalize_list_kernel(QueryBatch qb,
                  reinterpret_cast<uint32_t *>(out_dists[q]));
 }
 
+// The queries a round finished (count read on the device, so that the launch
+// can sit in a captured graph): each workgroup takes every gridDim-th one.
+// r-neighbour queries (k = 0xFFFFFFFF) have no top-k rows and are skipped.
+__global__ __launch_bounds__(MIH_BLOCK) void finalize_done_kernel(QueryBatch qb, const uint32_t *list,
+                                                                  const uint32_t *count,
+                                                                  const uint64_t *out_ids,
+                                                                  const uint64_t *out_dists)
+{
+    const uint32_t n = *count;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const uint32_t q = list[i];
+        if (qb.k[q] == 0xFFFFFFFFu) continue;
+        finalize_one(qb, q, reinterpret_cast<uint32_t *>(out_ids[q]),
+                     reinterpret_cast<uint32_t *>(out_dists[q]));
+        __syncthreads();   // finalize_one's shared state is reused by the next query
+    }
+}
+
 __global__ __launch_bounds__(MIH_BLOCK) void find_overflow_kernel(QueryBatch qb, uint32_t *list,
                                                                   uint32_t *count)
 {
@@ -170,6 +188,15 @@ hipError_t finalize_list(const QueryBatch &qb, const uint32_t *list, uint32_t nl
 {
     if (nlist == 0) return hipSuccess;
     finalize_list_kernel<<<nlist, MIH_BLOCK, 0, s>>>(qb, list, out_ids, out_dists);
+    return hipGetLastError();
+}
+
+hipError_t finalize_done(const QueryBatch &qb, const uint32_t *list, const uint32_t *count,
+                         const uint64_t *out_ids, const uint64_t *out_dists, uint32_t grid,
+                         hipStream_t s)
+{
+    if (grid == 0) return hipSuccess;
+    finalize_done_kernel<<<grid, MIH_BLOCK, 0, s>>>(qb, list, count, out_ids, out_dists);
     return hipGetLastError();
 }
 
