@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--nq", type=int, default=None, help="override the number of queries")
     ap.add_argument("--k", type=int, default=None, help="override k (single value)")
     ap.add_argument("--m", type=int, default=None, help="override the number of substrings")
-    ap.add_argument("--table-mode", default="auto", choices=["auto", "direct", "sorted", "grouped"])
+    ap.add_argument("--table-mode", default="auto", choices=["auto", "direct", "sorted", "grouped", "heads"])
     ap.add_argument("--codes-mode", default="auto", choices=["auto", "inline", "indirect"])
     ap.add_argument("--linscan-steps", type=int, default=None)
     ap.add_argument("--no-linscan", action="store_true")

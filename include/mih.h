@@ -67,7 +67,11 @@ typedef enum mih_table_mode {
     MIH_TABLE_AUTO = 0,
     MIH_TABLE_DIRECT = 1,
     MIH_TABLE_SORTED = 2,
-    MIH_TABLE_GROUPED = 3
+    MIH_TABLE_GROUPED = 3,
+    MIH_TABLE_HEADS = 4      /* 64-bit codes: DIRECT whose offsets sit beside each
+                                bucket's first code in 16-byte entries (2^s + 1
+                                of them per table), so that a one-code bucket
+                                costs one line; needs INLINE codes */
 } mih_table_mode;
 
 /* Where candidate codes are read during verification.  INLINE: each table
@@ -99,7 +103,7 @@ typedef struct mih_index mih_index;   /* opaque, owned by the library */
 typedef struct mih_index_info {
     uint64_t n;
     uint32_t bits, m;
-    uint32_t table_mode;          /* MIH_TABLE_DIRECT, _SORTED or _GROUPED  */
+    uint32_t table_mode;          /* MIH_TABLE_DIRECT, _SORTED, _GROUPED or _HEADS */
     uint32_t codes_mode;          /* MIH_CODES_INLINE or MIH_CODES_INDIRECT */
     uint32_t sub_len[MIH_M_MAX];  /* substring lengths s_j                  */
     uint32_t sub_start[MIH_M_MAX];/* first bit of substring j               */
@@ -126,6 +130,9 @@ typedef struct mih_table_view {
                                     bits 0..31 occupancy of values 32g..32g+31,
                                     bits 32..63 position of the first code
                                     with value >= 32g; else NULL            */
+    const uint64_t *heads;       /* HEADS: [2^len + 1] pairs of words: the
+                                    bucket's first code (0 if empty), then its
+                                    offset in the low 32 bits; else NULL    */
 } mih_table_view;
 
 /* Per-call counters of the multi-index search (sums over the queries). */

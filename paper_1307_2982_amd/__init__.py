@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libmih.so")
 
 SENTINEL = 0xFFFFFFFF
 K_MAX = 4096
-TABLE_MODES = {"auto": 0, "direct": 1, "sorted": 2, "grouped": 3}
+TABLE_MODES = {"auto": 0, "direct": 1, "sorted": 2, "grouped": 3, "heads": 4}
 CODES_MODES = {"auto": 0, "inline": 1, "indirect": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error",
           4: "unsupported", 5: "no capacity"}
@@ -51,7 +51,7 @@ class TableView(ctypes.Structure):
     _fields_ = [("offsets", ctypes.c_void_p), ("keys", ctypes.c_void_p), ("dir", ctypes.c_void_p),
                 ("ids", ctypes.c_void_p), ("codes", ctypes.c_void_p), ("len", ctypes.c_uint32),
                 ("start", ctypes.c_uint32), ("dir_bits", ctypes.c_uint32), ("pad", ctypes.c_uint32),
-                ("occupancy", ctypes.c_void_p), ("groups", ctypes.c_void_p)]
+                ("occupancy", ctypes.c_void_p), ("groups", ctypes.c_void_p), ("heads", ctypes.c_void_p)]
 
 
 class QueryStats(ctypes.Structure):
@@ -258,7 +258,8 @@ class Index:
         _check(load().mih_index_get_info(self._h, ctypes.byref(inf)), "mih_index_get_info")
         m = inf.m
         return {"n": inf.n, "bits": inf.bits, "m": m,
-                "table_mode": {1: "direct", 2: "sorted", 3: "grouped"}.get(inf.table_mode, inf.table_mode),
+                "table_mode": {1: "direct", 2: "sorted", 3: "grouped", 4: "heads"}.get(inf.table_mode,
+                                                                                      inf.table_mode),
                 "codes_mode": {1: "inline", 2: "indirect"}.get(inf.codes_mode, inf.codes_mode),
                 "sub_len": list(inf.sub_len[:m]), "sub_start": list(inf.sub_start[:m]),
                 "dir_bits": list(inf.dir_bits[:m]), "device_bytes": inf.device_bytes,
@@ -311,6 +312,8 @@ class Index:
             out["occupancy"] = _copy_device(v.occupancy, max((1 << v.len) // 32, 1), torch.int32)
         if v.groups:
             out["groups"] = _copy_device(v.groups, max((1 << v.len) // 32, 1), torch.int64)
+        if v.heads:
+            out["heads"] = _copy_device(v.heads, 2 * ((1 << v.len) + 1), torch.int64).view(-1, 2)
         return out
 
     def rnn(self, queries: torch.Tensor, r, stats: bool = False):

@@ -531,9 +531,12 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
             seen[o.bit_order[p]] = 1;
         }
     }
-    if (o.table_mode > MIH_TABLE_GROUPED || o.codes_mode > MIH_CODES_INDIRECT) return MIH_ERR_INVALID;
-    // a GROUPED table finds a bucket by scanning the codes in table order
-    if (o.table_mode == MIH_TABLE_GROUPED && o.codes_mode == MIH_CODES_INDIRECT) return MIH_ERR_INVALID;
+    if (o.table_mode > MIH_TABLE_HEADS || o.codes_mode > MIH_CODES_INDIRECT) return MIH_ERR_INVALID;
+    // GROUPED tables scan, and HEADS tables read, the codes in table order
+    if ((o.table_mode == MIH_TABLE_GROUPED || o.table_mode == MIH_TABLE_HEADS) &&
+        o.codes_mode == MIH_CODES_INDIRECT)
+        return MIH_ERR_INVALID;
+    if (o.table_mode == MIH_TABLE_HEADS && bits != 64) return MIH_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
 
     mih_index *ix = new (std::nothrow) mih_index();
@@ -557,7 +560,7 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
         }
     }
     const uint32_t lg = ceil_log2(n + 1);
-    uint64_t direct_bytes = 0, sorted_bytes = 0, grouped_bytes = 0, max_entries = n + 1;
+    uint64_t direct_bytes = 0, sorted_bytes = 0, grouped_bytes = 0, heads_bytes = 0, max_entries = n + 1;
     for (uint32_t j = 0; j < m; ++j) {
         uint32_t p = lg > 3 ? lg - 3 : 1;
         if (p > ix->len[j]) p = ix->len[j];
@@ -565,6 +568,8 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
         ix->dir_bits[j] = p;
         direct_bytes += ((1ull << ix->len[j]) + 1) * 4 + std::max<uint64_t>((1ull << ix->len[j]) / 32, 1) * 4;
         grouped_bytes += std::max<uint64_t>((1ull << ix->len[j]) / 32, 1) * 8;
+        heads_bytes += ((1ull << ix->len[j]) + 1) * sizeof(BucketHead) +
+                       std::max<uint64_t>((1ull << ix->len[j]) / 32, 1) * 4;
         sorted_bytes += n * 4 + ((1ull << p) + 1) * 4;
         max_entries = std::max<uint64_t>(max_entries, (1ull << ix->len[j]) + 1);
     }
@@ -583,13 +588,18 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     if (o.table_mode == MIH_TABLE_DIRECT) ix->table_mode = MIH_TABLE_DIRECT;
     else if (o.table_mode == MIH_TABLE_SORTED) ix->table_mode = MIH_TABLE_SORTED;
     else if (o.table_mode == MIH_TABLE_GROUPED) ix->table_mode = MIH_TABLE_GROUPED;
+    else if (o.table_mode == MIH_TABLE_HEADS) ix->table_mode = MIH_TABLE_HEADS;
     else ix->table_mode = need + direct_bytes <= budget ? MIH_TABLE_DIRECT : MIH_TABLE_SORTED;
     need += ix->table_mode == MIH_TABLE_DIRECT ? direct_bytes
-          : ix->table_mode == MIH_TABLE_SORTED ? sorted_bytes : grouped_bytes;
-    // the offsets of a GROUPED table exist only while it is built
-    const uint64_t build_off_bytes = ix->table_mode == MIH_TABLE_GROUPED ? (max_entries + 1) * 4 : 0;
+          : ix->table_mode == MIH_TABLE_SORTED ? sorted_bytes
+          : ix->table_mode == MIH_TABLE_GROUPED ? grouped_bytes : heads_bytes;
+    // the plain offsets of GROUPED and HEADS tables exist only while they are built
+    const uint64_t build_off_bytes =
+        (ix->table_mode == MIH_TABLE_GROUPED || ix->table_mode == MIH_TABLE_HEADS) ? (max_entries + 1) * 4 : 0;
     need += build_off_bytes;
-    if (o.codes_mode == MIH_CODES_INLINE || ix->table_mode == MIH_TABLE_GROUPED) ix->codes_mode = MIH_CODES_INLINE;
+    if (o.codes_mode == MIH_CODES_INLINE || ix->table_mode == MIH_TABLE_GROUPED ||
+        ix->table_mode == MIH_TABLE_HEADS)
+        ix->codes_mode = MIH_CODES_INLINE;
     else if (o.codes_mode == MIH_CODES_INDIRECT) ix->codes_mode = MIH_CODES_INDIRECT;
     else ix->codes_mode = need + inline_bytes <= budget ? MIH_CODES_INLINE : MIH_CODES_INDIRECT;
     if (ix->codes_mode == MIH_CODES_INLINE) need += inline_bytes;
@@ -642,6 +652,16 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
                 if (e == hipSuccess && (e = ix->alloc((void **)&occ, std::max<uint64_t>(nb / 32, 1) * 4)) == hipSuccess)
                     e = mih::occupancy_bits(off, nb, occ, s);
                 T.occ = occ;
+            } else if (ix->table_mode == MIH_TABLE_HEADS) {
+                // offsets (kept until the codes are in table order) and the
+                // occupancy map; the heads follow the inline codes below
+                const uint64_t nb = 1ull << T.len;
+                uint32_t *off = (uint32_t *)toff.ptr;
+                e = mih::bucket_offsets(keys, n, 0, off, nb, (uint32_t *)tmp.ptr, s);
+                uint32_t *occ = nullptr;
+                if (e == hipSuccess && (e = ix->alloc((void **)&occ, std::max<uint64_t>(nb / 32, 1) * 4)) == hipSuccess)
+                    e = mih::occupancy_bits(off, nb, occ, s);
+                T.occ = occ;
             } else if (ix->table_mode == MIH_TABLE_GROUPED) {
                 const uint64_t nb = 1ull << T.len;
                 uint32_t *off = (uint32_t *)toff.ptr;
@@ -667,6 +687,16 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
                 if ((e = ix->alloc((void **)&tc, n * 8 * W)) != hipSuccess) { st = from_hip(e); break; }
                 if ((e = mih::gather_codes(codes, ids, n, W, tc, s)) != hipSuccess) { st = from_hip(e); break; }
                 T.codes = tc;
+            }
+            if (ix->table_mode == MIH_TABLE_HEADS) {
+                const uint64_t nb = 1ull << T.len;
+                BucketHead *head = nullptr;
+                if ((e = ix->alloc((void **)&head, (nb + 1) * sizeof(BucketHead))) != hipSuccess ||
+                    (e = mih::bucket_heads((const uint32_t *)toff.ptr, nb, T.codes, head, s)) != hipSuccess) {
+                    st = from_hip(e);
+                    break;
+                }
+                T.head = head;
             }
             if ((e = hipStreamSynchronize(s)) != hipSuccess) { st = from_hip(e); break; }
         }
@@ -940,6 +970,7 @@ mih_status mih_index_table(const mih_index *idx, uint32_t j, mih_table_view *vie
     view->pad = 0;
     view->occupancy = T.occ;
     view->groups = T.grp;
+    view->heads = reinterpret_cast<const uint64_t *>(T.head);
     return MIH_OK;
 }
 

@@ -152,6 +152,23 @@ __global__ __launch_bounds__(MIH_BLOCK) void group_records_kernel(const uint32_t
     }
 }
 
+__global__ __launch_bounds__(MIH_BLOCK) void bucket_heads_kernel(const uint32_t *__restrict__ off,
+                                                                 uint64_t nbuckets,
+                                                                 const uint64_t *__restrict__ codes,
+                                                                 BucketHead *head)
+{
+    uint64_t v = (uint64_t)blockIdx.x * MIH_BLOCK + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * MIH_BLOCK;
+    for (; v <= nbuckets; v += stride) {
+        const uint32_t b0 = off[v];
+        BucketHead h;
+        h.code = (v < nbuckets && off[v + 1] > b0) ? codes[b0] : 0ull;
+        h.start = b0;
+        h.pad = 0;
+        head[v] = h;
+    }
+}
+
 template <int W>
 __global__ __launch_bounds__(MIH_BLOCK) void gather_codes_kernel(const uint64_t *__restrict__ codes,
                                                                  const uint32_t *__restrict__ ids,
@@ -238,6 +255,13 @@ hipError_t bucket_offsets(const uint32_t *sorted_keys, uint64_t n, uint32_t shif
 hipError_t occupancy_bits(const uint32_t *off, uint64_t nbuckets, uint32_t *occ, hipStream_t s)
 {
     occupancy_kernel<<<grid_for((nbuckets + 31) / 32), MIH_BLOCK, 0, s>>>(off, nbuckets, occ);
+    return hipGetLastError();
+}
+
+hipError_t bucket_heads(const uint32_t *off, uint64_t nbuckets, const uint64_t *codes, BucketHead *head,
+                        hipStream_t s)
+{
+    bucket_heads_kernel<<<grid_for(nbuckets + 1), MIH_BLOCK, 0, s>>>(off, nbuckets, codes, head);
     return hipGetLastError();
 }
 

@@ -190,7 +190,8 @@ void Engine::fill_args(MihArgs &A) const
     A.bits = ix_->bits;
     A.t_all = ix_->t_all;
     A.tm = ix_->table_mode == MIH_TABLE_SORTED ? TM_SORTED
-         : ix_->table_mode == MIH_TABLE_GROUPED ? TM_GROUPED : TM_DIRECT;
+         : ix_->table_mode == MIH_TABLE_GROUPED ? TM_GROUPED
+         : ix_->table_mode == MIH_TABLE_HEADS ? TM_HEADS : TM_DIRECT;
     A.inline_codes = ix_->codes_mode == MIH_CODES_INLINE;
     A.chunk = ix_->tuning.chunk;
     A.J = ix_->tuning.probes_per_lane;

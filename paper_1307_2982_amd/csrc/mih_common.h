@@ -200,6 +200,14 @@ __device__ __forceinline__ void block_bitonic_sort(uint64_t *v, uint32_t P)
     }
 }
 
+// HEADS tables: a bucket's offset beside its first code (16 bytes, so that
+// the entries of v and v + 1 usually share a line).
+struct BucketHead {
+    uint64_t code;    // the bucket's first code in table order (0 if empty)
+    uint32_t start;   // offset of the bucket: codes with a smaller value
+    uint32_t pad;
+};
+
 // `count` packed entries moved from entry offset src to entry offset dst.
 struct RnnMove {
     uint64_t src, dst;
@@ -215,6 +223,7 @@ struct TableDev {
     uint32_t pad0;
     const uint32_t *off;     // DIRECT: [2^len + 1]
     const uint32_t *occ;     // DIRECT: [2^len / 32 (at least 1)] bit v: bucket v non-empty
+    const BucketHead *head;  // HEADS: [2^len + 1]
     const uint64_t *grp;     // GROUPED: [2^len / 32 (at least 1)]: bits 0..31 occupancy of
                              // buckets 32g..32g+31, bits 32..63 position of the group's first code
     const uint32_t *keys;    // SORTED: [n]
@@ -297,6 +306,10 @@ hipError_t gather_codes(const uint64_t *codes, const uint32_t *ids, uint64_t n, 
                         uint64_t *out, hipStream_t s);
 // occ[v / 32] bit v % 32 = [off[v + 1] > off[v]] for v < nbuckets.
 hipError_t occupancy_bits(const uint32_t *off, uint64_t nbuckets, uint32_t *occ, hipStream_t s);
+// head[v] = {first code of bucket v (codes in table order, 64-bit), off[v]}
+// for v <= nbuckets.
+hipError_t bucket_heads(const uint32_t *off, uint64_t nbuckets, const uint64_t *codes,
+                        BucketHead *head, hipStream_t s);
 // grp[g] = (off[32 g] << 32) | occupancy bits of buckets 32g..32g+31.
 hipError_t group_records(const uint32_t *off, uint64_t nbuckets, uint64_t *grp, hipStream_t s);
 

@@ -6,7 +6,7 @@
 namespace mih {
 
 // Table layouts as the search kernel sees them.
-enum { TM_DIRECT = 0, TM_SORTED = 1, TM_GROUPED = 2 };
+enum { TM_DIRECT = 0, TM_SORTED = 1, TM_GROUPED = 2, TM_HEADS = 3 };
 
 // Active queries that share the same next step form a group; its work items
 // are the chunks of that step's shell for each of its queries, numbered

@@ -168,7 +168,7 @@ template <int W, int TM, bool INLINE, int J>
 __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t key_base,
                              uint32_t nbits, uint32_t rho, uint32_t rb, uint32_t re,
                              const uint32_t (*binom)[MIH_BINOM_N], uint32_t *stage_pos,
-                             uint32_t *stage_cum, WaveStats &ws)
+                             uint32_t *stage_cum, uint64_t *stage_code, WaveStats &ws)
 {
     const uint32_t lane = lane_id();
     const uint32_t m = A.m;
@@ -182,6 +182,7 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
         const uint32_t r0 = base + lane * J;
         const uint32_t nmy = r0 < re ? (re - r0 < (uint32_t)J ? re - r0 : (uint32_t)J) : 0u;
         uint32_t lo[J], cnt[J], keys[J];
+        uint64_t head_code[J];   // HEADS: the first code of each bucket
         uint32_t mask = nmy ? unrank_mask(r0, rho, nbits, binom) : 0u;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -207,7 +208,7 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
                     gbase[j] = (uint32_t)(rec >> 32) + __popc(occ & ((1u << bit) - 1u));
                 }
             }
-        } else if (TM == mih::TM_DIRECT && A.occ_filter) {
+        } else if (TM == mih::TM_HEADS || (TM == mih::TM_DIRECT && A.occ_filter)) {
             occ_bits = 0;
 #pragma unroll
             for (int j = 0; j < J; ++j)
@@ -221,6 +222,11 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
                 const uint32_t key = keys[j];
                 if (TM == mih::TM_GROUPED) {
                     group_scan<W>(T, A.n, key, gbase[j], lo[j], cnt[j]);
+                } else if (TM == mih::TM_HEADS) {
+                    const BucketHead h = T.head[key];
+                    lo[j] = h.start;
+                    cnt[j] = T.head[(uint64_t)key + 1].start - h.start;
+                    head_code[j] = h.code;
                 } else if (TM == mih::TM_DIRECT) {
                     const uint32_t b0 = T.off[key];
                     const uint32_t b1 = T.off[(uint64_t)key + 1];
@@ -261,6 +267,7 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
             if (cnt[j]) {
                 stage_pos[p] = lo[j];
                 stage_cum[p] = c;
+                if (TM == mih::TM_HEADS) stage_code[p] = head_code[j];
                 ++p;
                 c += cnt[j];
             }
@@ -281,7 +288,9 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
             uint64_t code[W];
             uint32_t id = 0;
             if (live) {
-                if (INLINE) {
+                if (TM == mih::TM_HEADS && e == stage_cum[bl]) {
+                    code[0] = stage_code[bl];   // a bucket's first code came with its offsets
+                } else if (INLINE) {
                     load_code<W>(T.codes + (uint64_t)pos * W, code);
                 } else {
                     id = T.ids[pos];
@@ -326,6 +335,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
     __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
     __shared__ uint32_t stage_pos[kWaves][MIH_WAVE * J];
     __shared__ uint32_t stage_cum[kWaves][MIH_WAVE * J];
+    __shared__ uint64_t stage_code[kWaves][TM == mih::TM_HEADS ? MIH_WAVE * J : 1];
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += MIH_BLOCK)
         binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
@@ -359,7 +369,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
         uint64_t gq[W];
         const uint32_t a0 = t - rp * A.m;
         process_step<W, TM, INLINE, J>(A, q, t, query_key<W>(A, q, a0, gq), A.tables[a0].len, rp, rb, re,
-                                       binom, stage_pos[wave], stage_cum[wave], ws);
+                                       binom, stage_pos[wave], stage_cum[wave], stage_code[wave], ws);
         if (G.ipq != 1) continue;
         // the whole step belonged to this wave: keep going while steps are small
         for (;;) {
@@ -373,7 +383,8 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
             if (Mn) {
                 const uint32_t an = tn - rpn * A.m;
                 process_step<W, TM, INLINE, J>(A, q, tn, query_key<W>(A, q, an, gq), A.tables[an].len, rpn,
-                                               0, Mn, binom, stage_pos[wave], stage_cum[wave], ws);
+                                               0, Mn, binom, stage_pos[wave], stage_cum[wave],
+                                               stage_code[wave], ws);
             }
             t = tn;
             if (lane == 0) A.t[q] = t;
@@ -410,6 +421,9 @@ __device__ __forceinline__ void first_lookup(const TableDev &T, uint32_t occ_fil
         const uint64_t rec = T.grp[key >> 5];
         pa = (uint32_t)rec;
         pb = (uint32_t)(rec >> 32);
+    } else if (TM == mih::TM_HEADS) {
+        pa = T.occ[key >> 5];
+        pb = 0;
     } else if (TM == mih::TM_DIRECT) {
         if (occ_filter) {
             pa = T.occ[key >> 5];
@@ -435,6 +449,11 @@ __device__ __forceinline__ void second_lookup(const TableDev &T, uint64_t n, uin
     if (TM == mih::TM_GROUPED) {
         const uint32_t bit = key & 31;
         if ((pa >> bit) & 1u) group_scan<W>(T, n, key, pb + __popc(pa & ((1u << bit) - 1u)), lo, cnt);
+    } else if (TM == mih::TM_HEADS) {
+        if ((pa >> (key & 31)) & 1u) {
+            lo = T.head[key].start;
+            cnt = T.head[(uint64_t)key + 1].start - lo;
+        }
     } else if (TM == mih::TM_DIRECT) {
         if (occ_filter) {
             if ((pa >> (key & 31)) & 1u) {
@@ -873,6 +892,9 @@ const void *round_kernel_w(uint32_t tm, bool inline_codes, uint32_t J, bool swee
                             : round_kernel_ptr<W, mih::TM_SORTED, false>(J, sweep);
     case mih::TM_GROUPED:   // the group scan reads the codes in table order
         return inline_codes ? round_kernel_ptr<W, mih::TM_GROUPED, true>(J, sweep) : nullptr;
+    case mih::TM_HEADS:     // 64-bit codes in table order only
+        if constexpr (W == 1) return inline_codes ? round_kernel_ptr<W, mih::TM_HEADS, true>(J, sweep) : nullptr;
+        return nullptr;
     default: return nullptr;
     }
 }

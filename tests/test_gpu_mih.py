@@ -13,7 +13,7 @@ from gpu_util import as_u32, assert_same, to_dev
 pytestmark = pytest.mark.gpu
 
 MODES = [("direct", "inline"), ("direct", "indirect"), ("sorted", "inline"), ("sorted", "indirect"),
-         ("grouped", "inline")]
+         ("grouped", "inline"), ("heads", "inline")]
 
 
 @pytest.fixture(scope="module")
@@ -83,7 +83,8 @@ def test_mih_uniform_64_m3_all_modes(mih, tmode, cmode):
 
 
 @pytest.mark.parametrize("tmode,occ,shift", [("direct", 0, 0), ("direct", 1, 0), ("grouped", 0, 0),
-                                              ("direct", 1, 9), ("grouped", 0, 9), ("sorted", 0, 9)])
+                                              ("direct", 1, 9), ("grouped", 0, 9), ("sorted", 0, 9),
+                                              ("heads", 1, 0), ("heads", 1, 9)])
 def test_mih_launch_tunings_agree(mih, tmode, occ, shift):
     # Every launch tuning (probes per lane, chunk, occupancy filter, swept
     # steps and their partition size) returns the same exact result and
@@ -107,6 +108,31 @@ def test_mih_launch_tunings_agree(mih, tmode, occ, shift):
                 assert_same(ids, dists, oi, od, what)
                 assert st["probes"] == probes, what
     idx.close()
+
+
+def test_heads_tables_match_algorithm1(mih):
+    # HEADS (64-bit codes): entry v holds the offset of bucket v and, for a
+    # non-empty bucket, its first code in (value, id) order
+    n = 40_003
+    codes = datagen.uniform_codes(n, 64, 302)
+    ref = oracle.MihCpu(codes, 3)
+    idx = mih.build(to_dev(codes), 3, table_mode="heads")
+    assert idx.info()["table_mode"] == "heads"
+    for j in range(3):
+        values, ids = ref.table(j)
+        tab = idx.table(j)
+        heads = tab["heads"].numpy()
+        nb = 1 << tab["len"]
+        start = np.searchsorted(values, np.arange(nb + 1, dtype=np.uint64)).astype(np.int64)
+        assert np.array_equal(heads[:, 1] & 0xFFFFFFFF, start)
+        nonempty = start[1:] > start[:-1]
+        first = np.zeros(nb, dtype=np.uint64)
+        first[nonempty] = codes[ids[start[:-1][nonempty]], 0]
+        assert np.array_equal(heads[:nb, 0].view(np.uint64), first)
+    with pytest.raises(mih.MihError):
+        mih.build(to_dev(datagen.uniform_codes(100, 128, 303)), 4, table_mode="heads")
+    idx.close()
+    ref.close()
 
 
 def test_mih_probe_count_equals_closed_form(mih):
@@ -162,7 +188,7 @@ def test_mih_per_query_k_and_k_beyond_n(mih):
     assert_same(ids, dists, oi, od, "per-query k")
 
 
-@pytest.mark.parametrize("tmode", ["auto", "grouped"])
+@pytest.mark.parametrize("tmode", ["auto", "grouped", "heads"])
 def test_mih_duplicates_overflow_rerun(mih, tmode):
     # 5000 copies of one code: the query equal to it finds them all in one
     # bucket; the buffer (2048) overflows and the query is re-run exactly.

@@ -53,7 +53,7 @@ def planted(query: np.ndarray, count: int, max_flips: int, seed: int) -> np.ndar
     return out
 
 
-@pytest.mark.parametrize("tmode,cmode", [("direct", "inline"), ("sorted", "indirect")])
+@pytest.mark.parametrize("tmode,cmode", [("direct", "inline"), ("sorted", "indirect"), ("heads", "inline")])
 def test_mih_rnn_uniform_radii(mih, tmode, cmode):
     n, nq = 200_003, 24
     codes = datagen.uniform_codes(n, 64, 61)
