@@ -230,7 +230,6 @@ void row_offsets(const std::vector<uint32_t> &k, std::vector<uint64_t> &off)
     for (size_t i = 0; i < k.size(); ++i) { off[i] = acc; acc += k[i]; }
 }
 
-uint32_t mih_cap(uint32_t k) { return k == 0 ? 0u : std::max<uint32_t>(2048u, 8u * k); }
 uint32_t scan_cap(uint32_t k) { return k == 0 ? 0u : std::max<uint32_t>(4096u, 16u * k); }
 
 }  // namespace

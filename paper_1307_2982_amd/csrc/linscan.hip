@@ -90,13 +90,6 @@ __device__ __forceinline__ uint32_t bcnt_acc_v(uint32_t x, uint32_t acc_v)
     return r;
 }
 
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
-{
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
 // queries and qb.tau hold nbatches * QB rows; rows from qb.nq on are padding
 // whose bound test is forced to fail.
 template <int W, int QB, int R>

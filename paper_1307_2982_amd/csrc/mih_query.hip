@@ -375,7 +375,8 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
         for (;;) {
             const uint32_t tau = tighten_tau(A.qb, q, __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q)));
             if (tau <= t || t >= A.t_all || t >= A.max_t[q]) break;
-            if (A.budget[q] && __builtin_amdgcn_readfirstlane(load_relaxed(A.uniq + q)) >= A.budget[q]) break;
+            if (A.budget[q] && (uint32_t)__builtin_amdgcn_readfirstlane(load_relaxed(A.uniq + q)) >= A.budget[q])
+                break;
             const uint32_t tn = t + 1;
             const uint32_t rpn = tn / A.m;
             const uint32_t Mn = binom_calc(A.tables[tn - rpn * A.m].len, rpn);
