@@ -52,7 +52,9 @@ def parse():
                     help="wall-time budget of the CPU oracle sample")
     ap.add_argument("--threads", type=int, default=None, help="host threads for generation/oracle")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch tuning")
-    ap.add_argument("--autotune-sample", type=int, default=2000)
+    ap.add_argument("--autotune-sample", type=int, default=0,
+                    help="queries the autotuner times (default: as many as the timed batch); "
+                         "they are the rows of the query stream that follow the timed ones")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=100)
@@ -312,13 +314,19 @@ def main():
         del arr, pos
         torch.cuda.synchronize()
 
-    # ---------------- launch tuning picked on a sample of the queries
+    # ---------------- launch tuning picked on other queries of the same
+    # distribution, as many as the timed batch unless told otherwise (how
+    # much each round can run ahead depends on the batch size)
     tuned = None
+    ns = 0
     if not args.no_autotune:
         t = time.time()
-        ns = min(nq, args.autotune_sample)
-        tuned = idx.autotune(dq[:ns], k_arg if isinstance(k_arg, int) else k_arg[:ns])
-        log(f"autotuned on {ns} queries in {time.time() - t:.1f}s: {tuned}")
+        ns = args.autotune_sample or nq
+        tq = to_device(datagen.query_codes(kind, ns, bits, first_row=nq, threads=threads))
+        tk = datagen.choice_u32(ns, ks, datagen.SEED_K, first=nq).tolist() if mixed_k else k_arg
+        tuned = idx.autotune(tq, tk)
+        del tq
+        log(f"autotuned on {ns} other queries in {time.time() - t:.1f}s: {tuned}")
 
     # ---------------- multi-index hashing
     for _ in range(args.warmup):
@@ -656,6 +664,7 @@ def main():
         "mih_step_ms": [round(x, 2) for x in step_ms],
         "tuning": idx.get_tuning(),
         "autotuned": tuned is not None,
+        "autotune_queries": ns,
         "tuning_sweep": sweep,
         "m_sweep": m_sweep,
         "choose_m": chosen_m,

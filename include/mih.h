@@ -296,11 +296,20 @@ typedef struct mih_tuning {
                                   probes reach 2^s >> sweep_shift is run
                                   partition by partition of the key space   */
     uint32_t sweep_bits;       /* key bits per sweep partition, 10..32        */
+    uint32_t lookahead;        /* 1..MIH_LOOKAHEAD_MAX: most steps (Algorithm 3)
+                                  a query may run in one round.  Above 1, a
+                                  round whose steps would leave waves of the
+                                  search kernel idle also runs the following
+                                  steps of its queries, lowest first, while
+                                  they fit.  Exact searches only: approximate
+                                  ones (mih_knn_approx) always use 1        */
 } mih_tuning;
+
+#define MIH_LOOKAHEAD_MAX 16u
 
 /* Current tuning of an index (defaults after mih_build: 4, 8192, 0, the
  * occupancy filter on for DIRECT tables of substrings of 26 bits or more,
- * sweep off, 18 sweep bits). */
+ * sweep off, 18 sweep bits, lookahead MIH_LOOKAHEAD_MAX). */
 mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
 
 /* Replace the tuning; MIH_ERR_INVALID (index unchanged) if a field is out of

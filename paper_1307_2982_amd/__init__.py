@@ -78,7 +78,8 @@ class ScanStats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("probes_per_lane", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
                 ("blocks_per_cu", ctypes.c_uint32), ("occupancy_filter", ctypes.c_uint32),
-                ("sweep_shift", ctypes.c_uint32), ("sweep_bits", ctypes.c_uint32)]
+                ("sweep_shift", ctypes.c_uint32), ("sweep_bits", ctypes.c_uint32),
+                ("lookahead", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -270,15 +271,21 @@ class Index:
         _check(load().mih_get_tuning(self._h, ctypes.byref(t)), "mih_get_tuning")
         return t.as_dict()
 
-    def set_tuning(self, probes_per_lane: int, chunk: int, blocks_per_cu: int = 0,
-                   occupancy_filter: int | None = None, sweep_shift: int | None = None,
-                   sweep_bits: int | None = None):
+    def set_tuning(self, probes_per_lane: int | None = None, chunk: int | None = None,
+                   blocks_per_cu: int | None = None, occupancy_filter: int | None = None,
+                   sweep_shift: int | None = None, sweep_bits: int | None = None,
+                   lookahead: int | None = None):
         """Launch tuning (speed only); fields left as None keep their value."""
         cur = self.get_tuning()
+        probes_per_lane = cur["probes_per_lane"] if probes_per_lane is None else probes_per_lane
+        chunk = cur["chunk"] if chunk is None else chunk
+        blocks_per_cu = cur["blocks_per_cu"] if blocks_per_cu is None else blocks_per_cu
         occupancy_filter = cur["occupancy_filter"] if occupancy_filter is None else occupancy_filter
         sweep_shift = cur["sweep_shift"] if sweep_shift is None else sweep_shift
         sweep_bits = cur["sweep_bits"] if sweep_bits is None else sweep_bits
-        t = Tuning(probes_per_lane, chunk, blocks_per_cu, occupancy_filter, sweep_shift, sweep_bits)
+        lookahead = cur["lookahead"] if lookahead is None else lookahead
+        t = Tuning(probes_per_lane, chunk, blocks_per_cu, occupancy_filter, sweep_shift, sweep_bits,
+                   lookahead)
         _check(load().mih_set_tuning(self._h, ctypes.byref(t)), "mih_set_tuning")
 
     def autotune(self, queries: torch.Tensor, k) -> dict:

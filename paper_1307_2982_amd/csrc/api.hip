@@ -414,6 +414,7 @@ mih_status engine_batch(mih::Engine &eng, const uint64_t *queries, uint32_t nq,
 {
     std::vector<uint64_t> completed;
     eng.set_count_unique(budget != 0);
+    eng.set_lookahead(max_t == 0xFFFFFFFFu && budget == 0);
     eng.submit(queries, nq, k.data(), row_off.data(), out_ids, out_dists, max_t, budget);
     uint64_t guard = 0;
     while (!eng.idle()) {
@@ -948,6 +949,7 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning)
         return MIH_ERR_INVALID;
     if (tuning->blocks_per_cu > 64 || tuning->occupancy_filter > 1) return MIH_ERR_INVALID;
     if (tuning->sweep_shift > 32 || tuning->sweep_bits < 10 || tuning->sweep_bits > 32) return MIH_ERR_INVALID;
+    if (tuning->lookahead < 1 || tuning->lookahead > MIH_LOOKAHEAD_MAX) return MIH_ERR_INVALID;
     std::lock_guard<std::mutex> lock(idx->mu);
     idx->tuning = *tuning;
     idx->tuning_version++;

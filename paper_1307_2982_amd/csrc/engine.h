@@ -58,7 +58,7 @@ struct mih_index {
     std::vector<void *> allocs;
     uint64_t device_bytes = 0;
     double build_ms = 0;
-    mih_tuning tuning = {4, 8192, 0, 0, 0, 18};
+    mih_tuning tuning = {4, 8192, 0, 0, 0, 18, MIH_LOOKAHEAD_MAX};
     uint32_t tuning_version = 0;
     std::mutex mu;
     std::unique_ptr<mih::Engine> batch_engine;   // reused by mih_knn calls
@@ -100,6 +100,10 @@ public:
     // Count distinct codes per query (needed by budgets; off by default).
     // Only while the engine is idle.
     void set_count_unique(bool on) { count_unique_ = on; }
+    // Let rounds run queries ahead by several steps when they would leave
+    // waves idle (exact searches only: an approximate query's result depends
+    // on the steps it ran).  On by default; only while the engine is idle.
+    void set_lookahead(bool on) { lookahead_ = on; }
     // A request of nq r-neighbour queries with per-query radius (host).  Its
     // results are taken with take_rnn() once the ticket has completed.
     uint64_t submit_rnn(const uint64_t *queries, uint32_t nq, const uint32_t *radius);
@@ -159,6 +163,7 @@ private:
     uint32_t *tmp_list_ = nullptr, *tmp_cnt_ = nullptr;
     uint32_t *max_t_ = nullptr, *budget_ = nullptr, *uniq_ = nullptr;
     bool count_unique_ = false, graph_count_unique_ = false;
+    bool lookahead_ = true, graph_lookahead_ = true;
     uint64_t *out_ids_ = nullptr, *out_dists_ = nullptr;
     Group *groups_ = nullptr;
     Control *ctrl_ = nullptr;

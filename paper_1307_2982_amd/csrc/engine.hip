@@ -203,6 +203,9 @@ void Engine::fill_args(MihArgs &A) const
     A.budget = budget_;
     A.uniq = uniq_;
     A.sweep_bits = ix_->tuning.sweep_bits;
+    // lookahead fills the waves of the round kernel
+    A.look_max = lookahead_ ? std::min<uint32_t>(std::max<uint32_t>(ix_->tuning.lookahead, 1u), kLookMax) : 1u;
+    A.look_items = A.look_max > 1 ? round_grid_ * (MIH_BLOCK / MIH_WAVE) : 0u;
     A.qb = qb_;
     A.t = t_;
     A.out_ids = out_ids_;
@@ -373,6 +376,8 @@ hipError_t Engine::capture_graph()
     if (ix_->tuning.blocks_per_cu && ix_->tuning.blocks_per_cu < per_cu_sweep)
         per_cu_sweep = ix_->tuning.blocks_per_cu;
     sweep_grid_ = cu_count() * per_cu_sweep;
+    fill_args(A);   // again, now that the round's grid is known
+    graph_lookahead_ = lookahead_;
     if (!use_graph_) {
         graph_tuning_version_ = ix_->tuning_version;
         graph_count_unique_ = count_unique_;
@@ -421,7 +426,7 @@ hipError_t Engine::run_round()
 {
     hipError_t e;
     if (graph_tuning_version_ != ix_->tuning_version || (use_graph_ && !graph_exec_) ||
-        graph_count_unique_ != count_unique_) {
+        graph_count_unique_ != count_unique_ || graph_lookahead_ != lookahead_) {
         if ((e = capture_graph()) != hipSuccess) return e;
     }
     if (use_graph_ && graph_exec_) {

@@ -8,16 +8,23 @@ namespace mih {
 // Table layouts as the search kernel sees them.
 enum { TM_DIRECT = 0, TM_SORTED = 1, TM_GROUPED = 2, TM_HEADS = 3 };
 
+// Most steps one round may run ahead for a group of queries.
+constexpr uint32_t kLookMax = MIH_LOOKAHEAD_MAX;
+
 // Active queries that share the same next step form a group; its work items
 // are the chunks of that step's shell for each of its queries, numbered
-// from item_start, query-major.
+// from item_start, query-major.  When the round would leave waves idle, a
+// group also takes its next steps (up to kLookMax in all): the items of
+// query i of the group are then the chunks of steps t, t + 1, ..., in order.
 // A group whose step has many more probes than its table has buckets per
 // cache line runs in the sweep kernel instead (ipq = 0 there): its items
 // are (key partition of 2^sweep_bits values, chunk of kSweepQueries queries).
 struct Group {
-    uint32_t t;           // step to process
+    uint32_t t;           // first step to process
     uint32_t count;       // queries in the group
-    uint32_t ipq;         // work items per query: ceil(C(s_a, r') / chunk), 0 when swept
+    uint32_t ipq;         // work items per query: step_items[steps], 0 when swept
+    uint32_t steps;       // steps t .. t + steps - 1 run in this round
+    uint32_t step_items[kLookMax + 1];   // items per query before step t + u
     uint32_t slot_start;  // first position of the group in the active list
     uint64_t item_start;  // first work item of the group
     uint32_t sweep_bits;  // swept: L, the key bits enumerated inside a partition; else 0
@@ -68,6 +75,9 @@ struct MihArgs {
     uint32_t occ_filter;      // DIRECT: test the occupancy bitmap before the offsets
     uint32_t sweep_shift;     // sweep a group when its probes reach 2^s >> sweep_shift (0: never)
     uint32_t sweep_bits;      // key bits enumerated inside one sweep partition
+    uint32_t look_items;      // a round may take further steps of its groups
+                              // while its items stay within this (0: never)
+    uint32_t look_max;        // most steps of a group per round (<= kLookMax)
     QueryBatch qb;            // per-slot state (qb.queries is slot storage)
     uint32_t *t;              // [slots] current step of each query
     uint32_t *max_t;          // [slots] last step allowed (approximate search), or ~0

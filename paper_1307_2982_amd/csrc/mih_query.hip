@@ -33,6 +33,11 @@ namespace {
 // J: masks per lane per iteration (a tuning knob; 64 J buckets are staged
 // per wave and iteration).
 constexpr uint32_t kWaves = MIH_BLOCK / MIH_WAVE;
+// Candidates per lane and pass of the candidate walk: more loads in flight
+// per wave, against the registers that keep them (64-bit codes: 2 keeps the
+// kernel at six waves per SIMD).
+template <int W>
+constexpr int walk_depth() { return W == 1 ? 2 : 4; }
 
 __device__ __forceinline__ uint32_t binom_calc(uint32_t n, uint32_t r)
 {
@@ -276,52 +281,77 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
         ws.probes += __shfl(wave_inclusive_sum(nmy), MIH_WAVE - 1, MIH_WAVE);
         ws.candidates += TC;
 
-        for (uint32_t e0 = 0; e0 < TC; e0 += MIH_WAVE) {
-            const uint32_t e = e0 + lane;
-            const bool live = e < TC;
-            uint32_t bl = 0, bh = NE;
-            while (bh - bl > 1) {
-                uint32_t mid = (bl + bh) >> 1;
-                if (stage_cum[mid] <= e) bl = mid; else bh = mid;
+        constexpr int kWalk = walk_depth<W>();
+        // the candidates are walked kWalk x 64 at a time: lane l takes
+        // e0 + 64 u + l for u < kWalk, so every load instruction covers 64
+        // consecutive table positions, and the kWalk loads of a lane are in
+        // flight together
+        for (uint32_t e0 = 0; e0 < TC; e0 += MIH_WAVE * kWalk) {
+            const uint32_t nu = (TC - e0 + MIH_WAVE - 1) / MIH_WAVE;   // live slices (wave-uniform)
+            uint32_t bl[kWalk], pos[kWalk], id[kWalk];
+            bool live[kWalk];
+            uint64_t code[kWalk][W];
+            // staged bucket of each candidate: the last one whose running
+            // count is <= e (branch-free halving, the searches interleaved)
+#pragma unroll
+            for (int u = 0; u < kWalk; ++u) bl[u] = 0;
+            for (uint32_t len = NE; len > 1;) {
+                const uint32_t half = len >> 1;
+#pragma unroll
+                for (int u = 0; u < kWalk; ++u)
+                    if ((uint32_t)u < nu && stage_cum[bl[u] + half] <= e0 + u * MIH_WAVE + lane) bl[u] += half;
+                len -= half;
             }
-            const uint32_t pos = live ? stage_pos[bl] + (e - stage_cum[bl]) : 0u;
-            uint64_t code[W];
-            uint32_t id = 0;
-            if (live) {
-                if (TM == mih::TM_HEADS && e == stage_cum[bl]) {
-                    code[0] = stage_code[bl];   // a bucket's first code came with its offsets
-                } else if (INLINE) {
-                    load_code<W>(T.codes + (uint64_t)pos * W, code);
+#pragma unroll
+            for (int u = 0; u < kWalk; ++u) {
+                const uint32_t e = e0 + u * MIH_WAVE + lane;
+                live[u] = e < TC;
+                pos[u] = live[u] ? stage_pos[bl[u]] + (e - stage_cum[bl[u]]) : 0u;
+                id[u] = 0;
+                if (!INLINE && live[u]) id[u] = T.ids[pos[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kWalk; ++u) {
+                if (live[u]) {
+                    if (TM == mih::TM_HEADS && e0 + u * MIH_WAVE + lane == stage_cum[bl[u]]) {
+                        code[u][0] = stage_code[bl[u]];   // a bucket's first code came with its offsets
+                    } else if (INLINE) {
+                        load_code<W>(T.codes + (uint64_t)pos[u] * W, code[u]);
+                    } else {
+                        load_code<W>(A.codes + (uint64_t)id[u] * W, code[u]);
+                    }
                 } else {
-                    id = T.ids[pos];
-                    load_code<W>(A.codes + (uint64_t)id * W, code);
-                }
-            } else {
 #pragma unroll
-                for (int w = 0; w < W; ++w) code[w] = g[w];
-            }
-            const uint32_t d = hamming<W>(code, g);
-            // first encounter of the code (row a8); every candidate is tested
-            // when distinct codes are counted, else only those within tau
-            bool first = live && (A.count_unique || d <= tau);
-            if (first) {
-                uint64_t x[W];
-#pragma unroll
-                for (int w = 0; w < W; ++w) x[w] = code[w] ^ g[w];
-                for (uint32_t j = 0; j < m; ++j) {
-                    if (j == a) continue;
-                    const uint32_t dj = table_dist<W>(x, A.tables[j]);
-                    if (j < a ? dj <= rp : dj < rp) { first = false; break; }
+                    for (int w = 0; w < W; ++w) code[u][w] = g[w];
                 }
             }
-            if (A.count_unique) {
-                const uint64_t fb = __ballot(first);
-                if (fb && lane == 0) atomicAdd(A.uniq + q, (uint32_t)__popcll(fb));
+#pragma unroll
+            for (int u = 0; u < kWalk; ++u) {
+                if ((uint32_t)u >= nu) break;
+                const uint32_t d = hamming<W>(code[u], g);
+                // first encounter of the code (the de-duplication rule
+                // above); every candidate is tested when distinct codes are
+                // counted, else only those within tau
+                bool first = live[u] && (A.count_unique || d <= tau);
+                if (first) {
+                    uint64_t x[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) x[w] = code[u][w] ^ g[w];
+                    for (uint32_t j = 0; j < m; ++j) {
+                        if (j == a) continue;
+                        const uint32_t dj = table_dist<W>(x, A.tables[j]);
+                        if (j < a ? dj <= rp : dj < rp) { first = false; break; }
+                    }
+                }
+                if (A.count_unique) {
+                    const uint64_t fb = __ballot(first);
+                    if (fb && lane == 0) atomicAdd(A.uniq + q, (uint32_t)__popcll(fb));
+                }
+                const bool keep = first && d <= tau;
+                if (keep && INLINE) id[u] = T.ids[pos[u]];
+                append_candidates(A.qb, q, keep, d, id[u]);
+                if (__ballot(keep)) tau = tighten_tau(A.qb, q, tau);
             }
-            const bool keep = first && d <= tau;
-            if (keep && INLINE) id = T.ids[pos];
-            append_candidates(A.qb, q, keep, d, id);
-            if (__ballot(keep)) tau = tighten_tau(A.qb, q, tau);
         }
         wave_lds_sync();
         const uint32_t g_tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
@@ -356,12 +386,19 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
             uint32_t mid = (gl + gh) >> 1;
             if (A.groups[mid].item_start <= item) gl = mid; else gh = mid;
         }
-        const mih::Group G = A.groups[gl];
-        const uint64_t rel = item - G.item_start;
-        const uint32_t slot = G.slot_start + (uint32_t)(rel / G.ipq);
-        const uint32_t part = (uint32_t)(rel % G.ipq);
+        gl = __builtin_amdgcn_readfirstlane(gl);
+        const mih::Group *G = A.groups + gl;
+        const uint32_t ipq = G->ipq, steps = G->steps;
+        const uint64_t rel = item - G->item_start;
+        const uint32_t slot = G->slot_start + (uint32_t)(rel / ipq);
+        uint32_t part = (uint32_t)(rel % ipq);
+        // the step of the window that holds the item (steps without probes
+        // hold no items and are passed over)
+        uint32_t u = 0;
+        while (u + 1 < steps && G->step_items[u + 1] <= part) ++u;
+        part -= G->step_items[u];
         const uint32_t q = A.active[slot];
-        uint32_t t = G.t;
+        uint32_t t = G->t + u;
         const uint32_t rp = t / A.m;
         const uint32_t M = binom_calc(A.tables[t - rp * A.m].len, rp);
         const uint32_t rb = part * chunk;
@@ -370,7 +407,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
         const uint32_t a0 = t - rp * A.m;
         process_step<W, TM, INLINE, J>(A, q, t, query_key<W>(A, q, a0, gq), A.tables[a0].len, rp, rb, re,
                                        binom, stage_pos[wave], stage_cum[wave], stage_code[wave], ws);
-        if (G.ipq != 1) continue;
+        if (ipq != 1 || steps != 1) continue;
         // the whole step belonged to this wave: keep going while steps are small
         for (;;) {
             const uint32_t tau = tighten_tau(A.qb, q, __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q)));
@@ -754,9 +791,19 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
 // Start of a round (one workgroup): the queries that survived the last
 // advance and the newly admitted ones (at step 0) form the active list,
 // grouped by step; the work-item numbering follows the groups.
+//
+// Lookahead.  When the groups' steps make fewer items than the waves the
+// round kernel runs (look_items), groups also take their following steps,
+// lowest steps first, one step per group and pass, while the round stays
+// within that many items.  Taking a step early changes no result: a code is
+// accepted only at its first step whatever the order the steps run in, the
+// bound tau only ever shrinks to a value no smaller than the final k-th
+// distance, and after the round every step up to the last one taken has run,
+// which is all that the termination test (Proposition 2) needs.  A query of
+// the group then resumes after its window's last step.
 __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
 {
-    extern __shared__ uint32_t bins[];   // [nbins] counts, then [nbins] cursors
+    extern __shared__ uint32_t bins[];   // [nbins] counts, [nbins] cursors, [nbins] window ends
     __shared__ uint32_t s_active, s_groups;
     __shared__ unsigned long long s_items, s_sweep;
     const uint32_t tid = threadIdx.x;
@@ -764,7 +811,8 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
     mih::Control *ctrl = A.ctrl;
     const uint32_t n_old = ctrl->n_active;
     const uint32_t n_new = ctrl->n_new;
-    for (uint32_t i = tid; i < 2 * nbins; i += 1024) bins[i] = 0;
+    uint32_t *last = bins + 2 * nbins;
+    for (uint32_t i = tid; i < 3 * nbins; i += 1024) bins[i] = 0;
     __syncthreads();
     for (uint32_t i = tid; i < n_old; i += 1024) {
         uint32_t nt = A.next_t[i];
@@ -778,6 +826,7 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
         for (uint32_t b = 0; b < nbins; ++b) {
             uint32_t c = bins[b];
             bins[nbins + b] = slot;
+            last[b] = b;
             if (!c) continue;
             const uint32_t rp = b / A.m;
             const uint32_t s = A.tables[b - rp * A.m].len;
@@ -785,9 +834,9 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
             mih::Group G;
             G.t = b;
             G.count = c;
+            G.steps = 1;
+            G.step_items[0] = 0;
             G.slot_start = slot;
-            G.item_start = items;
-            G.sweep_start = sweep_items;
             // many probes per bucket line: run the step partition by partition
             const bool sweep = A.sweep_shift != 0 && s >= mih::kSweepMinBits &&
                                (uint64_t)c * M >= ((1ull << s) >> A.sweep_shift);
@@ -797,15 +846,50 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
                 G.ipq = 0;
                 G.sweep_bits = L;
                 G.sweep_qc = (c + mih::kSweepQueries - 1) / mih::kSweepQueries;
-                sweep_items += ((1ull << (s - L)) / mih::kSweepXcds) * G.sweep_qc;   // per XCD
             } else {
                 G.ipq = (M + A.chunk - 1) / A.chunk;
                 G.sweep_bits = 0;
                 G.sweep_qc = 0;
             }
+            G.step_items[1] = G.ipq;
             A.groups[ng++] = G;
             slot += c;
             items += (uint64_t)c * G.ipq;
+        }
+        // lookahead: pass u offers step t + u to every group that took all
+        // of its steps so far, while the round's items fit in look_items
+        for (uint32_t u = 1; u < A.look_max && items < A.look_items; ++u) {
+            bool grew = false;
+            for (uint32_t x = 0; x < ng; ++x) {
+                mih::Group &G = A.groups[x];
+                if (G.ipq == 0 || G.steps != u) continue;   // swept, or stopped growing
+                const uint32_t tn = G.t + u;
+                if (tn > A.t_all) continue;
+                const uint32_t rp = tn / A.m;
+                const uint32_t M = binom_calc(A.tables[tn - rp * A.m].len, rp);
+                const uint32_t ni = (M + A.chunk - 1) / A.chunk;
+                if (items + (uint64_t)G.count * ni > A.look_items) continue;
+                items += (uint64_t)G.count * ni;
+                G.ipq += ni;
+                G.step_items[u + 1] = G.ipq;
+                G.steps = u + 1;
+                last[G.t] = tn;
+                grew = true;
+            }
+            if (!grew) break;
+        }
+        // item and sweep numbering of the final groups
+        items = 0;
+        for (uint32_t x = 0; x < ng; ++x) {
+            mih::Group &G = A.groups[x];
+            G.item_start = items;
+            G.sweep_start = sweep_items;
+            items += (uint64_t)G.count * G.ipq;
+            if (G.ipq == 0) {
+                const uint32_t rp = G.t / A.m;
+                const uint32_t s = A.tables[G.t - rp * A.m].len;
+                sweep_items += ((1ull << (s - G.sweep_bits)) / mih::kSweepXcds) * G.sweep_qc;   // per XCD
+            }
         }
         s_active = slot;
         s_groups = ng;
@@ -813,11 +897,20 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
         s_sweep = sweep_items;
     }
     __syncthreads();
+    // a query whose group runs ahead resumes after the window's last step
     for (uint32_t i = tid; i < n_old; i += 1024) {
         uint32_t nt = A.next_t[i];
-        if (nt != 0xFFFFFFFFu) A.active_tmp[atomicAdd(&bins[nbins + nt], 1u)] = A.active[i];
+        if (nt != 0xFFFFFFFFu) {
+            const uint32_t q = A.active[i];
+            A.active_tmp[atomicAdd(&bins[nbins + nt], 1u)] = q;
+            if (last[nt] != nt) A.t[q] = last[nt];
+        }
     }
-    for (uint32_t i = tid; i < n_new; i += 1024) A.active_tmp[atomicAdd(&bins[nbins], 1u)] = A.new_slots[i];
+    for (uint32_t i = tid; i < n_new; i += 1024) {
+        const uint32_t q = A.new_slots[i];
+        A.active_tmp[atomicAdd(&bins[nbins], 1u)] = q;
+        if (last[0] != 0) A.t[q] = last[0];
+    }
     __syncthreads();
     const uint32_t total = s_active;
     for (uint32_t i = tid; i < total; i += 1024) A.active[i] = A.active_tmp[i];
@@ -946,7 +1039,7 @@ int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, 
 
 hipError_t mih_regroup(const MihArgs &A, hipStream_t s)
 {
-    const size_t lds = sizeof(uint32_t) * 2 * (A.t_all + 1);
+    const size_t lds = sizeof(uint32_t) * 3 * (A.t_all + 1);
     mih_regroup_kernel<<<1, 1024, lds, s>>>(A);
     return hipGetLastError();
 }

@@ -87,9 +87,10 @@ def test_mih_uniform_64_m3_all_modes(mih, tmode, cmode):
                                               ("heads", 1, 0), ("heads", 1, 9)])
 def test_mih_launch_tunings_agree(mih, tmode, occ, shift):
     # Every launch tuning (probes per lane, chunk, occupancy filter, swept
-    # steps and their partition size) returns the same exact result and
-    # examines the same buckets: a swept step enumerates, per partition of
-    # the key space, the masks whose high part the partition fixes.
+    # steps and their partition size) returns the same exact result and,
+    # one step per round, examines the same buckets: a swept step
+    # enumerates, per partition of the key space, the masks whose high part
+    # the partition fixes.  Running ahead (lookahead) may examine more.
     n, nq, m, k = 150_001, 60, 3, 50
     codes = datagen.uniform_codes(n, 64, 51)
     queries = datagen.uniform_codes(nq, 64, 52)
@@ -102,11 +103,15 @@ def test_mih_launch_tunings_agree(mih, tmode, occ, shift):
     for J in (4, 8, 16):
         for chunk in (64 * J * 2, 64 * J * 32):
             for sbits in ((16, 20) if shift else (18,)):
-                idx.set_tuning(J, chunk, 0, occ, shift, sbits)
-                ids, dists, st = idx.knn(dq, k, stats=True)
-                what = f"{tmode} occ={occ} sweep={shift}/{sbits} J={J} chunk={chunk}"
-                assert_same(ids, dists, oi, od, what)
-                assert st["probes"] == probes, what
+                for look in (1, 16):
+                    idx.set_tuning(J, chunk, 0, occ, shift, sbits, look)
+                    ids, dists, st = idx.knn(dq, k, stats=True)
+                    what = f"{tmode} occ={occ} sweep={shift}/{sbits} J={J} chunk={chunk} look={look}"
+                    assert_same(ids, dists, oi, od, what)
+                    if look == 1:
+                        assert st["probes"] == probes, what
+                    else:
+                        assert st["probes"] >= probes, what
     idx.close()
 
 
@@ -142,6 +147,7 @@ def test_mih_probe_count_equals_closed_form(mih):
     codes = datagen.uniform_codes(n, 64, 11)
     queries = datagen.uniform_codes(nq, 64, 12)
     idx = mih.build(to_dev(codes), m)
+    idx.set_tuning(lookahead=1)   # one step per round: no step runs early
     ids, dists, st = idx.knn(to_dev(queries), k, stats=True)
     oi, od = oracle.knn(codes, queries, k)
     assert_same(ids, dists, oi, od, "probe count run")
