@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--serve-loads", default="0.5,0.9",
                     help="fractions of the closed-loop capacity to replay the stream at")
     ap.add_argument("--serve-slots", type=int, default=16384)
+    ap.add_argument("--serve-tuning", default="",
+                    help="launch tuning fields for the serving leg only, e.g. chunk=8192,lookahead=1 "
+                         "(default: the batch tuning with chunk at most 8192)")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the search over a grid of launch tunings")
     ap.add_argument("--m-sweep", default="",
@@ -483,7 +486,17 @@ def main():
         serve_k = datagen.CONFIGS[args.config]["ks"] if args.config != 4 else (1, 10, 100, 1000)
         if args.config == 5:
             serve_k = (1, 10, 100)
+        batch_t = idx.get_tuning()
+        # rounds of a serving loop often hold few queries: smaller work items
+        # spread them over more waves (the batch-tuned chunk is for full batches)
+        serve_t = {"chunk": min(batch_t["chunk"], 8192)}
+        if args.serve_tuning:
+            serve_t = {f: int(v) for f, v in (kv.split("=") for kv in args.serve_tuning.split(","))}
+        idx.set_tuning(**serve_t)
+        log(f"serving tuning: {idx.get_tuning()}")
         serving = serve_bench(mih, idx, kind, bits, serve_k, args, log)
+        serving["tuning"] = idx.get_tuning()
+        idx.set_tuning(**batch_t)
 
     # ---------------- linear scan
     lin = None

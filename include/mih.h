@@ -301,7 +301,9 @@ typedef struct mih_tuning {
                                   round whose steps would leave waves of the
                                   search kernel idle also runs the following
                                   steps of its queries, lowest first, while
-                                  they fit.  Exact searches only: approximate
+                                  its work items fit in the resident waves
+                                  and its shell masks in four passes of
+                                  them.  Exact searches only: approximate
                                   ones (mih_knn_approx) always use 1        */
 } mih_tuning;
 

@@ -206,6 +206,7 @@ void Engine::fill_args(MihArgs &A) const
     // lookahead fills the waves of the round kernel
     A.look_max = lookahead_ ? std::min<uint32_t>(std::max<uint32_t>(ix_->tuning.lookahead, 1u), kLookMax) : 1u;
     A.look_items = A.look_max > 1 ? round_grid_ * (MIH_BLOCK / MIH_WAVE) : 0u;
+    A.look_masks = (uint64_t)A.look_items * MIH_WAVE * A.J * kLookPasses;
     A.qb = qb_;
     A.t = t_;
     A.out_ids = out_ids_;

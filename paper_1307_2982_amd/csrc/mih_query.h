@@ -10,6 +10,8 @@ enum { TM_DIRECT = 0, TM_SORTED = 1, TM_GROUPED = 2, TM_HEADS = 3 };
 
 // Most steps one round may run ahead for a group of queries.
 constexpr uint32_t kLookMax = MIH_LOOKAHEAD_MAX;
+// Shell masks a round may grow to by lookahead, in passes of every wave.
+constexpr uint32_t kLookPasses = 4;
 
 // Active queries that share the same next step form a group; its work items
 // are the chunks of that step's shell for each of its queries, numbered
@@ -78,6 +80,7 @@ struct MihArgs {
     uint32_t look_items;      // a round may take further steps of its groups
                               // while its items stay within this (0: never)
     uint32_t look_max;        // most steps of a group per round (<= kLookMax)
+    uint64_t look_masks;      // ... and while its shell masks stay within this
     QueryBatch qb;            // per-slot state (qb.queries is slot storage)
     uint32_t *t;              // [slots] current step of each query
     uint32_t *max_t;          // [slots] last step allowed (approximate search), or ~0

@@ -795,7 +795,8 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
 // Lookahead.  When the groups' steps make fewer items than the waves the
 // round kernel runs (look_items), groups also take their following steps,
 // lowest steps first, one step per group and pass, while the round stays
-// within that many items.  Taking a step early changes no result: a code is
+// within that many items and within look_masks shell masks (a few passes
+// of every wave: past that, the extra steps would lengthen the round).  Taking a step early changes no result: a code is
 // accepted only at its first step whatever the order the steps run in, the
 // bound tau only ever shrinks to a value no smaller than the final k-th
 // distance, and after the round every step up to the last one taken has run,
@@ -822,7 +823,7 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
     __syncthreads();
     if (tid == 0) {
         uint32_t slot = 0, ng = 0;
-        uint64_t items = 0, sweep_items = 0;
+        uint64_t items = 0, sweep_items = 0, masks = 0;
         for (uint32_t b = 0; b < nbins; ++b) {
             uint32_t c = bins[b];
             bins[nbins + b] = slot;
@@ -855,10 +856,11 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
             A.groups[ng++] = G;
             slot += c;
             items += (uint64_t)c * G.ipq;
+            masks += (uint64_t)c * M;
         }
         // lookahead: pass u offers step t + u to every group that took all
         // of its steps so far, while the round's items fit in look_items
-        for (uint32_t u = 1; u < A.look_max && items < A.look_items; ++u) {
+        for (uint32_t u = 1; u < A.look_max && items < A.look_items && masks < A.look_masks; ++u) {
             bool grew = false;
             for (uint32_t x = 0; x < ng; ++x) {
                 mih::Group &G = A.groups[x];
@@ -868,8 +870,11 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
                 const uint32_t rp = tn / A.m;
                 const uint32_t M = binom_calc(A.tables[tn - rp * A.m].len, rp);
                 const uint32_t ni = (M + A.chunk - 1) / A.chunk;
-                if (items + (uint64_t)G.count * ni > A.look_items) continue;
+                if (items + (uint64_t)G.count * ni > A.look_items ||
+                    masks + (uint64_t)G.count * M > A.look_masks)
+                    continue;
                 items += (uint64_t)G.count * ni;
+                masks += (uint64_t)G.count * M;
                 G.ipq += ni;
                 G.step_items[u + 1] = G.ipq;
                 G.steps = u + 1;
