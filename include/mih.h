@@ -321,10 +321,13 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning);
 /* Time mih_knn over a grid of tunings (probes_per_lane 4, 8, 16; chunk of
  * 2, 8, 32 or 128 times 64 * probes_per_lane; all workgroups that fit; with and
  * without the occupancy filter on DIRECT tables; and, for substrings of 20
- * bits or more, sweeps with sweep_shift 3 and 18 or 20 sweep bits) on the
- * given sample of queries, keep the fastest in the index and write it to
+ * bits or more, sweeps with sweep_shift 3 and 18 or 20 sweep bits; the
+ * lookahead of the current tuning) on the given sample of queries, time the
+ * three fastest twice more, keep the fastest in the index and write it to
  * *chosen (may be NULL).  Results do not depend on the tuning, so the
- * sample only has to look like the real queries.  Arguments as mih_knn. */
+ * sample only has to look like the real queries (how far rounds run ahead
+ * depends on the batch size: a sample as large as the real batches tunes
+ * best).  Arguments as mih_knn. */
 mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
                         const uint32_t *k_per_query, void *stream, mih_tuning *chosen);
 
