@@ -52,6 +52,8 @@ def parse():
                     help="wall-time budget of the CPU oracle sample")
     ap.add_argument("--threads", type=int, default=None, help="host threads for generation/oracle")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch tuning")
+    ap.add_argument("--tuning", default="",
+                    help="launch tuning fields to set instead of autotuning, e.g. sweep_shift=3,sweep_bits=18")
     ap.add_argument("--autotune-sample", type=int, default=0,
                     help="queries the autotuner times (default: as many as the timed batch); "
                          "they are the rows of the query stream that follow the timed ones")
@@ -322,7 +324,10 @@ def main():
     # much each round can run ahead depends on the batch size)
     tuned = None
     ns = 0
-    if not args.no_autotune:
+    if args.tuning:
+        idx.set_tuning(**{f: int(v) for f, v in (kv.split("=") for kv in args.tuning.split(","))})
+        log(f"tuning set: {idx.get_tuning()}")
+    elif not args.no_autotune:
         t = time.time()
         ns = args.autotune_sample or nq
         tq = to_device(datagen.query_codes(kind, ns, bits, first_row=nq, threads=threads))
