@@ -364,9 +364,16 @@ def main():
     launches = max(1, st["search_launches"])
     achieved = alg_bytes / (kern_ms / 1e3) / 1e9 if kern_ms > 0 else 0.0
     traffic = None
+    lines = None
     if (n, bits, m, nq, tuple(ks)) == (1_000_000_000, 64, 2, 10_000, (100,)) and \
             (info["table_mode"], info["codes_mode"]) == ("direct", "inline"):
-        traffic, _ = counter_traffic("mih_round_kernel_1e9x64_m2_k100_counters.json", idx.get_tuning())
+        traffic, rec = counter_traffic("mih_round_kernel_1e9x64_m2_k100_counters.json", idx.get_tuning())
+        if traffic is not None:
+            # the reads are random 64 B lines, which FETCH_SIZE counts in full
+            per_launch = float(np.mean(rec["fetch_kib_per_launch"])) * 1024 / 64
+            lines = {"lines_per_launch": round(per_launch),
+                     "lines_per_s": round(per_launch / (kern_ms / launches / 1e3)),
+                     "plain_gather_reads_per_s": rec.get("random_read_calibration", {}).get("reads_per_s")}
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -378,6 +385,7 @@ def main():
         "alg_bytes_per_step": int(alg_bytes),
         "per_unit": {"probe_B": per_probe, "candidate_B": per_cand, "appended_B": 16},
         "probes_per_query": st["probes"] / nq, "candidates_per_query": st["candidates"] / nq,
+        "random_lines": lines,
     }
 
     # ---------------- launch tunings (speed only; results must not change)

@@ -36,10 +36,11 @@ struct Group {
 
 // Queries per sweep work item (one per lane), the smallest table that is
 // swept, and the number of XCDs the partitions are dealt to.
-constexpr uint32_t kSweepQueries = 64;
+constexpr uint32_t kSweepQueries = 64;   // at most one per lane
 constexpr uint32_t kSweepMinBits = 20;
 constexpr uint32_t kSweepXcds = 8;
 constexpr uint32_t kSweepBatch = 4;   // consecutive sweep items claimed at once
+static_assert(kSweepQueries <= MIH_WAVE, "one lane per query of a sweep item");
 
 // Device-resident control block of a search engine.
 struct Control {

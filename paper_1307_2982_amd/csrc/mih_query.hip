@@ -561,10 +561,10 @@ __device__ void sweep_item(const mih::MihArgs &A, const mih::Group &G, uint32_t 
         for (int w = 0; w < W; ++w) S.qg[lane][w] = g[w];
     }
     const uint32_t incl = wave_inclusive_sum(M);
-    S.qstart[lane] = incl - M;
-    if (lane == MIH_WAVE - 1) S.qstart[MIH_WAVE] = incl;
+    if (lane < mih::kSweepQueries) S.qstart[lane] = incl - M;
+    if (lane == mih::kSweepQueries - 1) S.qstart[mih::kSweepQueries] = incl;
     wave_lds_sync();
-    const uint32_t total = S.qstart[MIH_WAVE];
+    const uint32_t total = S.qstart[mih::kSweepQueries];
     ws.probes += total;
 
     for (uint32_t base = 0; base < total; base += MIH_WAVE * J) {
@@ -574,7 +574,7 @@ __device__ void sweep_item(const mih::MihArgs &A, const mih::Group &G, uint32_t 
         uint32_t cur = 0, mask = 0;
         if (nmy) {
             // the query whose masks contain flat index f0: last start <= f0
-            uint32_t l = 0, hh = MIH_WAVE;
+            uint32_t l = 0, hh = mih::kSweepQueries;
             while (hh - l > 1) {
                 const uint32_t mid = (l + hh) >> 1;
                 if (S.qstart[mid] <= f0) l = mid; else hh = mid;
