@@ -352,6 +352,20 @@ def main():
     mih_qps = nq / (mih_ms / 1e3)
     log(f"MIH: {mih_ms:.1f} ms/step -> {mih_qps:,.0f} queries/s; last step {stats[-1]}")
 
+    # ---------------- radius histogram: each query's k-th nearest distance
+    # (the radius its search had to reach), per value of k
+    dk = dists.reshape(-1).cpu().numpy().view(np.uint32)
+    ends = np.cumsum(k_list.astype(np.int64)) - 1
+    radius_hist = {}
+    for kv in sorted(set(int(x) for x in k_list)):
+        if kv == 0:
+            continue
+        sel = ends[(k_list == kv)]
+        r = dk[sel]
+        r = r[r != 0xFFFFFFFF]
+        vals, cnts = np.unique(r, return_counts=True)
+        radius_hist[str(kv)] = {str(int(v)): int(c) for v, c in zip(vals, cnts)}
+
     # ---------------- roofline of the search kernel
     st = stats[-1]
     if info["codes_mode"] == "inline":
@@ -688,6 +702,7 @@ def main():
         "parity": {"mih_vs_oracle_sample": parity_oracle,
                    "mih_vs_linscan_all": lin["parity_with_mih"] if lin else None},
         "mih_step_ms": [round(x, 2) for x in step_ms],
+        "radius_histogram": radius_hist,
         "tuning": idx.get_tuning(),
         "autotuned": tuned is not None,
         "autotune_queries": ns,
