@@ -307,11 +307,12 @@ typedef struct mih_tuning {
                                   ones (mih_knn_approx) always use 1        */
 } mih_tuning;
 
-#define MIH_LOOKAHEAD_MAX 16u
+#define MIH_LOOKAHEAD_MAX 32u
+#define MIH_LOOKAHEAD_DEFAULT 16u
 
 /* Current tuning of an index (defaults after mih_build: 4, 8192, 0, the
  * occupancy filter on for DIRECT tables of substrings of 26 bits or more,
- * sweep off, 18 sweep bits, lookahead MIH_LOOKAHEAD_MAX). */
+ * sweep off, 18 sweep bits, lookahead MIH_LOOKAHEAD_DEFAULT). */
 mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
 
 /* Replace the tuning; MIH_ERR_INVALID (index unchanged) if a field is out of

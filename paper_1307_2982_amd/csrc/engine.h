@@ -58,7 +58,7 @@ struct mih_index {
     std::vector<void *> allocs;
     uint64_t device_bytes = 0;
     double build_ms = 0;
-    mih_tuning tuning = {4, 8192, 0, 0, 0, 18, MIH_LOOKAHEAD_MAX};
+    mih_tuning tuning = {4, 8192, 0, 0, 0, 18, MIH_LOOKAHEAD_DEFAULT};
     uint32_t tuning_version = 0;
     std::mutex mu;
     std::unique_ptr<mih::Engine> batch_engine;   // reused by mih_knn calls

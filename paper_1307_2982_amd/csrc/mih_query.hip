@@ -400,7 +400,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
         const uint32_t q = A.active[slot];
         uint32_t t = G->t + u;
         const uint32_t rp = t / A.m;
-        const uint32_t M = binom_calc(A.tables[t - rp * A.m].len, rp);
+        const uint32_t M = binom[A.tables[t - rp * A.m].len][rp];
         const uint32_t rb = part * chunk;
         const uint32_t re = rb + chunk < M ? rb + chunk : M;
         uint64_t gq[W];
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
                 break;
             const uint32_t tn = t + 1;
             const uint32_t rpn = tn / A.m;
-            const uint32_t Mn = binom_calc(A.tables[tn - rpn * A.m].len, rpn);
+            const uint32_t Mn = binom[A.tables[tn - rpn * A.m].len][rpn];
             if (Mn > chunk) break;
             if (Mn) {
                 const uint32_t an = tn - rpn * A.m;
@@ -770,7 +770,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
     if (!(tau <= t || t >= A.t_all || t >= max_t || spent)) {
         for (uint32_t tn = t + 1; tn <= max_t; ++tn) {
             const uint32_t rp = tn / A.m;
-            if (binom_calc(A.tables[tn - rp * A.m].len, rp) > 0) { out = tn; break; }
+            if (rp <= A.tables[tn - rp * A.m].len) { out = tn; break; }   // C(s, r') > 0
             if (tau <= tn || tn >= A.t_all) break;
         }
     }
@@ -804,7 +804,11 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
 // the group then resumes after its window's last step.
 __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
 {
-    extern __shared__ uint32_t bins[];   // [nbins] counts, [nbins] cursors, [nbins] window ends
+    // [nbins] counts, [nbins] cursors, [nbins] window ends, then per group
+    // (at most one per bin) its first step, query count, items per query
+    // and steps taken: the serial part below works in LDS only
+    extern __shared__ uint32_t bins[];
+    __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
     __shared__ uint32_t s_active, s_groups;
     __shared__ unsigned long long s_items, s_sweep;
     const uint32_t tid = threadIdx.x;
@@ -813,7 +817,11 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
     const uint32_t n_old = ctrl->n_active;
     const uint32_t n_new = ctrl->n_new;
     uint32_t *last = bins + 2 * nbins;
+    uint32_t *g_t = bins + 3 * nbins, *g_count = bins + 4 * nbins;
+    uint32_t *g_ipq = bins + 5 * nbins, *g_steps = bins + 6 * nbins;
     for (uint32_t i = tid; i < 3 * nbins; i += 1024) bins[i] = 0;
+    for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += 1024)
+        binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
     __syncthreads();
     for (uint32_t i = tid; i < n_old; i += 1024) {
         uint32_t nt = A.next_t[i];
@@ -823,7 +831,7 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
     __syncthreads();
     if (tid == 0) {
         uint32_t slot = 0, ng = 0;
-        uint64_t items = 0, sweep_items = 0, masks = 0;
+        uint64_t items = 0, masks = 0;
         for (uint32_t b = 0; b < nbins; ++b) {
             uint32_t c = bins[b];
             bins[nbins + b] = slot;
@@ -831,69 +839,70 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
             if (!c) continue;
             const uint32_t rp = b / A.m;
             const uint32_t s = A.tables[b - rp * A.m].len;
-            const uint32_t M = binom_calc(s, rp);
-            mih::Group G;
-            G.t = b;
-            G.count = c;
-            G.steps = 1;
-            G.step_items[0] = 0;
-            G.slot_start = slot;
-            // many probes per bucket line: run the step partition by partition
+            const uint32_t M = binom[s][rp];
+            // many probes per bucket line: run the step partition by
+            // partition (sweep kernel; no items of the round kernel)
             const bool sweep = A.sweep_shift != 0 && s >= mih::kSweepMinBits &&
                                (uint64_t)c * M >= ((1ull << s) >> A.sweep_shift);
-            if (sweep) {
-                // at least kSweepXcds partitions: one share per XCD
-                const uint32_t L = A.sweep_bits < s - 3 ? A.sweep_bits : s - 3;
-                G.ipq = 0;
-                G.sweep_bits = L;
-                G.sweep_qc = (c + mih::kSweepQueries - 1) / mih::kSweepQueries;
-            } else {
-                G.ipq = (M + A.chunk - 1) / A.chunk;
-                G.sweep_bits = 0;
-                G.sweep_qc = 0;
-            }
-            G.step_items[1] = G.ipq;
-            A.groups[ng++] = G;
+            const uint32_t ipq = sweep ? 0u : (M + A.chunk - 1) / A.chunk;
+            g_t[ng] = b;
+            g_count[ng] = c;
+            g_ipq[ng] = ipq;
+            g_steps[ng] = 1;
+            A.groups[ng].step_items[0] = 0;
+            A.groups[ng].step_items[1] = ipq;
+            A.groups[ng].slot_start = slot;
+            ++ng;
             slot += c;
-            items += (uint64_t)c * G.ipq;
+            items += (uint64_t)c * ipq;
             masks += (uint64_t)c * M;
         }
         // lookahead: pass u offers step t + u to every group that took all
-        // of its steps so far, while the round's items fit in look_items
+        // of its steps so far, while the round's items and masks fit
         for (uint32_t u = 1; u < A.look_max && items < A.look_items && masks < A.look_masks; ++u) {
             bool grew = false;
             for (uint32_t x = 0; x < ng; ++x) {
-                mih::Group &G = A.groups[x];
-                if (G.ipq == 0 || G.steps != u) continue;   // swept, or stopped growing
-                const uint32_t tn = G.t + u;
+                if (g_ipq[x] == 0 || g_steps[x] != u) continue;   // swept, or stopped growing
+                const uint32_t tn = g_t[x] + u;
                 if (tn > A.t_all) continue;
                 const uint32_t rp = tn / A.m;
-                const uint32_t M = binom_calc(A.tables[tn - rp * A.m].len, rp);
+                const uint32_t M = binom[A.tables[tn - rp * A.m].len][rp];
                 const uint32_t ni = (M + A.chunk - 1) / A.chunk;
-                if (items + (uint64_t)G.count * ni > A.look_items ||
-                    masks + (uint64_t)G.count * M > A.look_masks)
-                    continue;
-                items += (uint64_t)G.count * ni;
-                masks += (uint64_t)G.count * M;
-                G.ipq += ni;
-                G.step_items[u + 1] = G.ipq;
-                G.steps = u + 1;
-                last[G.t] = tn;
+                const uint64_t c = g_count[x];
+                if (items + c * ni > A.look_items || masks + c * M > A.look_masks) continue;
+                items += c * ni;
+                masks += c * M;
+                g_ipq[x] += ni;
+                g_steps[x] = u + 1;
+                A.groups[x].step_items[u + 1] = g_ipq[x];
+                last[g_t[x]] = tn;
                 grew = true;
             }
             if (!grew) break;
         }
-        // item and sweep numbering of the final groups
+        // the final groups and their item and sweep numbering
         items = 0;
+        uint64_t sweep_items = 0;
         for (uint32_t x = 0; x < ng; ++x) {
             mih::Group &G = A.groups[x];
+            G.t = g_t[x];
+            G.count = g_count[x];
+            G.ipq = g_ipq[x];
+            G.steps = g_steps[x];
             G.item_start = items;
             G.sweep_start = sweep_items;
-            items += (uint64_t)G.count * G.ipq;
-            if (G.ipq == 0) {
-                const uint32_t rp = G.t / A.m;
-                const uint32_t s = A.tables[G.t - rp * A.m].len;
-                sweep_items += ((1ull << (s - G.sweep_bits)) / mih::kSweepXcds) * G.sweep_qc;   // per XCD
+            items += (uint64_t)g_count[x] * g_ipq[x];
+            G.sweep_bits = 0;
+            G.sweep_qc = 0;
+            if (g_ipq[x] == 0) {
+                // at least kSweepXcds partitions: one share per XCD
+                const uint32_t rp = g_t[x] / A.m;
+                const uint32_t s = A.tables[g_t[x] - rp * A.m].len;
+                const uint32_t L = A.sweep_bits < s - 3 ? A.sweep_bits : s - 3;
+                const uint32_t qc = (g_count[x] + mih::kSweepQueries - 1) / mih::kSweepQueries;
+                G.sweep_bits = L;
+                G.sweep_qc = qc;
+                sweep_items += ((1ull << (s - L)) / mih::kSweepXcds) * qc;   // per XCD
             }
         }
         s_active = slot;
@@ -1044,7 +1053,7 @@ int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, 
 
 hipError_t mih_regroup(const MihArgs &A, hipStream_t s)
 {
-    const size_t lds = sizeof(uint32_t) * 3 * (A.t_all + 1);
+    const size_t lds = sizeof(uint32_t) * 7 * (A.t_all + 1);
     mih_regroup_kernel<<<1, 1024, lds, s>>>(A);
     return hipGetLastError();
 }

@@ -36,7 +36,7 @@ def test_lookahead_exact_knn(mih, bits, m, kind, tmode, cmode):
     ks[6] = 0
     oi, od = oracle.knn(codes, queries, ks)
     runs = {}
-    for look in (1, 2, 5, 16):
+    for look in (1, 2, 5, 16, 32):
         idx.set_tuning(lookahead=look)
         ids, dists, st = idx.knn(dq, ks.tolist(), stats=True)
         assert_same(ids, dists, oi, od, f"{bits}/{m}/{tmode}/{cmode} look={look}")
@@ -56,7 +56,7 @@ def test_lookahead_k_beyond_n(mih):
     idx = mih.build(to_dev(codes), m)
     dq = to_dev(queries)
     oi, od = oracle.knn(codes, queries, k)
-    for look in (1, 16):
+    for look in (1, 16, 32):
         idx.set_tuning(lookahead=look)
         ids, dists = idx.knn(dq, k)
         assert_same(ids, dists, oi, od, f"k > n look={look}")
@@ -118,8 +118,10 @@ def test_lookahead_leaves_approximate_search_alone(mih):
 def test_lookahead_tuning_is_validated(mih):
     codes = datagen.uniform_codes(1000, 64, 407)
     idx = mih.build(to_dev(codes), 2)
-    for bad in (0, 17):
+    for bad in (0, 33):
         with pytest.raises(mih.MihError):
             idx.set_tuning(lookahead=bad)
     assert idx.get_tuning()["lookahead"] == 16
+    idx.set_tuning(lookahead=32)
+    assert idx.get_tuning()["lookahead"] == 32
     idx.close()
