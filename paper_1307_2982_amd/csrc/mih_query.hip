@@ -9,18 +9,20 @@
 // the bound tau of the candidate buffer this is the test tau <= t.
 //
 // De-duplication without per-query state.  A code h with substring distances
-// d_0..d_{m-1} is met at every step (r', a) with d_a = r'.  Steps are visited
-// in increasing t = m r' + a, so its first encounter is t_h = min_j (m d_j + j).
-// A candidate met at step (r', a) is accepted only if no table j gives an
-// earlier step: d_j > r' for j < a and d_j >= r' for j > a.  This keeps
-// exactly the codes the paper's per-query bitstring would keep (Section 6,
-// duplicate candidates), with no bitstring to clear.
+// d_0..d_{m-1} is met at every step (r', a) with d_a = r'.  In Algorithm 3's
+// order of increasing t = m r' + a its first encounter is t_h =
+// min_j (m d_j + j).  A candidate met at step (r', a) is accepted only if no
+// table j gives an earlier step: d_j > r' for j < a and d_j >= r' for j > a.
+// This keeps exactly the codes the paper's per-query bitstring would keep
+// (Section 6, duplicate candidates), with no bitstring to clear, and it does
+// not depend on the order in which the device happens to run the steps.
 //
 // Scheduling.  All queries of a call advance in rounds; a round performs one
-// step of every active query.  The buckets of a step are enumerated in
-// colexicographic order of the flip masks and split into work items of
-// `chunk` masks; a persistent kernel hands items to waves through an atomic
-// counter.  A step that fits in one item is processed by one wave, which
+// step of every active query, or several when it would otherwise leave
+// waves idle (lookahead, decided by the regroup kernel).  The buckets of a
+// step are enumerated in colexicographic order of the flip masks and split
+// into work items of `chunk` masks; a persistent kernel hands items to waves
+// through an atomic counter.  A step that fits in one item is processed by one wave, which
 // then carries on with the query's next steps while they remain that small
 // (the wave alone owns the query, so it can test termination itself).
 // Between rounds a small kernel tests termination, moves unfinished queries
