@@ -236,8 +236,8 @@ def weighted_pct(a, w, q):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
-              "multi-GPU path: run with --gpus 1", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the library has no "
+              "multi-GPU search; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

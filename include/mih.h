@@ -45,7 +45,7 @@ typedef enum mih_status {
     MIH_ERR_INVALID = 1,      /* bad argument: nothing was written            */
     MIH_ERR_NOMEM = 2,        /* device memory exhausted                       */
     MIH_ERR_DEVICE = 3,       /* HIP runtime or kernel failure                 */
-    MIH_ERR_UNSUPPORTED = 4,  /* valid request outside this build's limits     */
+    MIH_ERR_UNSUPPORTED = 4,  /* valid request outside the library's limits    */
     MIH_ERR_CAPACITY = 5      /* server: no free query slot or buffer memory   */
 } mih_status;
 
