@@ -5,8 +5,9 @@ or a small pool of codes repeated many times, so that distances tie and
 buckets overflow), a number of substrings, table and codes modes, a launch
 tuning (probes per lane, chunk, occupancy filter, sweep, lookahead), queries
 that include exact copies and near copies of database codes, per-query k
-(k = 0 and k > n among them) and an r-neighbour radius.  Every kNN row and
-every r-neighbour list must equal the oracle's, ids and distances both.
+(k = 0 and k > n among them) and an r-neighbour radius.  Every kNN row (of
+the multi-index search and of the linear scan) and every r-neighbour list
+must equal the oracle's, ids and distances both.
 """
 import numpy as np
 import pytest
@@ -87,6 +88,8 @@ def test_random_configuration(mih, case):
     ids, dists = idx.knn(dq, ks.tolist())
     oi, od = oracle.knn(codes, queries, ks)
     assert_same(ids, dists, oi, od, what)
+    li, ld = mih.linscan_knn(to_dev(codes), dq, ks.tolist())
+    assert_same(li, ld, oi, od, what + " (linear scan)")
     r = int(rng.integers(0, c["bits"] // 4 + 1))
     off, rid, rdist = idx.rnn(dq, r)
     off = off.cpu().numpy()
