@@ -44,7 +44,9 @@ def parse():
     ap.add_argument("--k", type=int, default=None, help="override k (single value)")
     ap.add_argument("--m", type=int, default=None, help="override the number of substrings")
     ap.add_argument("--table-mode", default="auto", choices=["auto", "direct", "sorted", "grouped", "heads"])
-    ap.add_argument("--codes-mode", default="auto", choices=["auto", "inline", "indirect"])
+    ap.add_argument("--codes-mode", default="auto", choices=["auto", "inline", "indirect", "mixed"])
+    ap.add_argument("--inline-tables", type=int, default=0,
+                    help="with --codes-mode mixed: tables that keep inline codes")
     ap.add_argument("--linscan-steps", type=int, default=None)
     ap.add_argument("--no-linscan", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -275,11 +277,12 @@ def main():
     log(f"copied to the device in {time.time() - t0:.1f}s")
 
     t0 = time.time()
-    idx = mih.build(dc, m, table_mode=args.table_mode, codes_mode=args.codes_mode)
+    idx = mih.build(dc, m, table_mode=args.table_mode, codes_mode=args.codes_mode,
+                    inline_tables=args.inline_tables)
     torch.cuda.synchronize()
     info = idx.info()
     log(f"built index in {time.time() - t0:.2f}s ({info['table_mode']}/{info['codes_mode']}, "
-        f"{info['device_bytes'] / 2**30:.1f} GiB)")
+        f"{info['inline_tables']} of {m} tables with inline codes, {info['device_bytes'] / 2**30:.1f} GiB)")
 
     if args.copy_calib > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
@@ -368,10 +371,10 @@ def main():
 
     # ---------------- roofline of the search kernel
     st = stats[-1]
-    if info["codes_mode"] == "inline":
-        per_cand = 8 * W
-    else:
-        per_cand = 4 + 8 * W
+    # a candidate costs its code, plus its id where the table reads codes
+    # through the ids (MIXED: in that share of the tables, the tables being
+    # alike in expectation)
+    per_cand = 8 * W + 4 * (1 - info["inline_tables"] / m)
     per_probe = 12 if info["table_mode"] == "sorted" else 8
     alg_bytes = st["probes"] * per_probe + st["candidates"] * per_cand + st["appended"] * 16
     kern_ms = st["search_kernel_ms"]
@@ -437,7 +440,8 @@ def main():
     if args.m_sweep:
         m_sweep = []
         for mm in [int(x) for x in args.m_sweep.split(",") if x]:
-            ix2 = mih.build(dc, mm, table_mode=args.table_mode, codes_mode=args.codes_mode)
+            ix2 = mih.build(dc, mm, table_mode=args.table_mode,
+                            codes_mode="auto" if args.codes_mode == "mixed" else args.codes_mode)
             ix2.knn(dq, k_arg)
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -466,7 +470,8 @@ def main():
         counts = mih.bit_cooccurrence(dc[:sample])
         cooc_ms = (time.perf_counter() - tc) * 1e3
         order = mih.greedy_bit_order(counts, sample, m, 0)
-        ix2 = mih.build(dc, m, table_mode=args.table_mode, codes_mode=args.codes_mode, bit_order=order)
+        ix2 = mih.build(dc, m, table_mode=args.table_mode, codes_mode=args.codes_mode, bit_order=order,
+                        inline_tables=args.inline_tables)
         if tuned is not None:
             ix2.set_tuning(**tuned)
         ix2.knn(dq, k_arg)
@@ -497,7 +502,7 @@ def main():
         kk = int(ks[-1]) if mixed_k else int(ks[0])
         t = time.time()
         best_m, trials = mih.choose_m(dc, kk, validation=1000, seed=9, table_mode=args.table_mode,
-                                      codes_mode=args.codes_mode)
+                                      codes_mode="auto" if args.codes_mode == "mixed" else args.codes_mode)
         chosen_m = {"k": kk, "validation": "1000 database rows (seeded permutation)", "best_m": best_m,
                     "model_radius": mih.model_radius(n, bits, kk), "heuristic_b_over_log2n":
                     round(bits / np.log2(n), 3), "trials": trials}
@@ -686,6 +691,7 @@ def main():
                                        f", {nq} queries, k drawn from {list(ks)}"),
             "n": n, "bits": bits, "m": m, "nq": nq, "k": list(ks),
             "table_mode": info["table_mode"], "codes_mode": info["codes_mode"],
+            "inline_tables": info["inline_tables"],
             "index_GiB": round(info["device_bytes"] / 2**30, 2), "build_ms": round(info["build_ms"], 1),
         },
         "p50_ms": serving["loads"][0]["p50_ms"] if serving and serving["loads"] else None,

@@ -77,11 +77,16 @@ typedef enum mih_table_mode {
 /* Where candidate codes are read during verification.  INLINE: each table
  * keeps a copy of the codes in its bucket order, so a bucket's codes are
  * contiguous (m * n * bits/8 extra bytes); INDIRECT: codes are gathered from
- * the caller's array through the ids.  AUTO: INLINE when it fits. */
+ * the caller's array through the ids; MIXED: the first inline_tables tables
+ * are INLINE, the others INDIRECT.  AUTO: INLINE when it fits, else as many
+ * INLINE tables as fit (MIXED), else INDIRECT.  With AUTO tables as well,
+ * SORTED is taken over DIRECT when DIRECT would not leave room for every
+ * table's codes and SORTED leaves room for more of them. */
 typedef enum mih_codes_mode {
     MIH_CODES_AUTO = 0,
     MIH_CODES_INLINE = 1,
-    MIH_CODES_INDIRECT = 2
+    MIH_CODES_INDIRECT = 2,
+    MIH_CODES_MIXED = 3
 } mih_codes_mode;
 
 typedef struct mih_build_opts {
@@ -96,6 +101,8 @@ typedef struct mih_build_opts {
                                     NULL: consecutive bits (bit_order[p] = p).
                                     Results never depend on it; speed may.  Not
                                     retained after the call. */
+    uint32_t inline_tables;      /* MIXED: INLINE tables, 1 <= inline_tables < m
+                                    (ignored by the other modes) */
 } mih_build_opts;
 
 typedef struct mih_index mih_index;   /* opaque, owned by the library */
@@ -104,7 +111,7 @@ typedef struct mih_index_info {
     uint64_t n;
     uint32_t bits, m;
     uint32_t table_mode;          /* MIH_TABLE_DIRECT, _SORTED, _GROUPED or _HEADS */
-    uint32_t codes_mode;          /* MIH_CODES_INLINE or MIH_CODES_INDIRECT */
+    uint32_t codes_mode;          /* MIH_CODES_INLINE, _INDIRECT or _MIXED  */
     uint32_t sub_len[MIH_M_MAX];  /* substring lengths s_j                  */
     uint32_t sub_start[MIH_M_MAX];/* first bit of substring j               */
     uint32_t dir_bits[MIH_M_MAX]; /* SORTED: directory bits per table       */
@@ -112,6 +119,9 @@ typedef struct mih_index_info {
     double build_ms;              /* wall time of mih_build                 */
     uint16_t bit_order[256];      /* the bit order of the substrings (the
                                      identity unless one was given)         */
+    uint32_t inline_tables;       /* tables 0 .. inline_tables - 1 keep their
+                                     codes inline (m for INLINE, 0 for
+                                     INDIRECT)                              */
 } mih_index_info;
 
 /* Device views of one table, for inspection and tests.  Pointers are owned
@@ -121,7 +131,7 @@ typedef struct mih_table_view {
     const uint32_t *keys;        /* SORTED: [n] substring values, else NULL */
     const uint32_t *dir;         /* SORTED: [2^dir_bits + 1], else NULL     */
     const uint32_t *ids;         /* [n] ids in bucket order                 */
-    const uint64_t *codes;       /* INLINE: [n][bits/64], else NULL         */
+    const uint64_t *codes;       /* an INLINE table: [n][bits/64], else NULL */
     uint32_t len, start, dir_bits, pad;
     const uint32_t *occupancy;   /* DIRECT: [max(2^len / 32, 1)] words, bit
                                     v % 32 of word v / 32 = [bucket v is

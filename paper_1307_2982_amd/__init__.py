@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libmih.so")
 SENTINEL = 0xFFFFFFFF
 K_MAX = 4096
 TABLE_MODES = {"auto": 0, "direct": 1, "sorted": 2, "grouped": 3, "heads": 4}
-CODES_MODES = {"auto": 0, "inline": 1, "indirect": 2}
+CODES_MODES = {"auto": 0, "inline": 1, "indirect": 2, "mixed": 3}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory", 3: "device error",
           4: "unsupported", 5: "no capacity"}
 
@@ -36,7 +36,8 @@ class MihError(RuntimeError):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("table_mode", ctypes.c_int), ("codes_mode", ctypes.c_int),
-                ("mem_budget_bytes", ctypes.c_uint64), ("bit_order", ctypes.c_void_p)]
+                ("mem_budget_bytes", ctypes.c_uint64), ("bit_order", ctypes.c_void_p),
+                ("inline_tables", ctypes.c_uint32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -44,7 +45,8 @@ class IndexInfo(ctypes.Structure):
                 ("table_mode", ctypes.c_uint32), ("codes_mode", ctypes.c_uint32),
                 ("sub_len", ctypes.c_uint32 * 64), ("sub_start", ctypes.c_uint32 * 64),
                 ("dir_bits", ctypes.c_uint32 * 64), ("device_bytes", ctypes.c_uint64),
-                ("build_ms", ctypes.c_double), ("bit_order", ctypes.c_uint16 * 256)]
+                ("build_ms", ctypes.c_double), ("bit_order", ctypes.c_uint16 * 256),
+                ("inline_tables", ctypes.c_uint32)]
 
 
 class TableView(ctypes.Structure):
@@ -261,7 +263,8 @@ class Index:
         return {"n": inf.n, "bits": inf.bits, "m": m,
                 "table_mode": {1: "direct", 2: "sorted", 3: "grouped", 4: "heads"}.get(inf.table_mode,
                                                                                       inf.table_mode),
-                "codes_mode": {1: "inline", 2: "indirect"}.get(inf.codes_mode, inf.codes_mode),
+                "codes_mode": {1: "inline", 2: "indirect", 3: "mixed"}.get(inf.codes_mode, inf.codes_mode),
+                "inline_tables": inf.inline_tables,
                 "sub_len": list(inf.sub_len[:m]), "sub_start": list(inf.sub_start[:m]),
                 "dir_bits": list(inf.dir_bits[:m]), "device_bytes": inf.device_bytes,
                 "build_ms": inf.build_ms, "bit_order": list(inf.bit_order[:inf.bits])}
@@ -379,9 +382,10 @@ class Index:
 
 
 def build(codes: torch.Tensor, m: int, table_mode: str = "auto", codes_mode: str = "auto",
-          mem_budget_bytes: int = 0, bit_order=None) -> Index:
+          mem_budget_bytes: int = 0, bit_order=None, inline_tables: int = 0) -> Index:
     """Build the m substring tables (Algorithm 1) on the device; bit_order
-    (a permutation of the code bits, Section 5.4) places the substrings."""
+    (a permutation of the code bits, Section 5.4) places the substrings;
+    codes_mode "mixed" keeps inline codes in the first inline_tables tables."""
     codes = _codes_arg(codes, "codes")
     n, W = codes.shape
     order = None
@@ -390,7 +394,7 @@ def build(codes: torch.Tensor, m: int, table_mode: str = "auto", codes_mode: str
             raise ValueError("bit_order must list every code bit once")
         order = (ctypes.c_uint16 * (64 * W))(*[int(b) for b in bit_order])
     opts = BuildOpts(TABLE_MODES[table_mode], CODES_MODES[codes_mode], mem_budget_bytes,
-                     ctypes.cast(order, ctypes.c_void_p) if order is not None else None)
+                     ctypes.cast(order, ctypes.c_void_p) if order is not None else None, inline_tables)
     h = ctypes.c_void_p()
     rc = load().mih_build(codes.data_ptr() if n else None, n, 64 * W, m, ctypes.byref(opts),
                           _stream(), ctypes.byref(h))

@@ -49,6 +49,15 @@ mih_status from_hip_at(hipError_t e, int line)
 
 bool bits_ok(uint32_t bits) { return bits == 64 || bits == 128 || bits == 192 || bits == 256; }
 
+// How many tables can keep an inline copy of the codes (per_table bytes
+// each) once `need` bytes are committed, within `budget`.
+uint32_t inline_tables_fit(uint64_t need, uint64_t budget, uint64_t per_table, uint32_t m)
+{
+    if (per_table == 0) return m;
+    if (need >= budget) return 0;
+    return (uint32_t)std::min<uint64_t>(m, (budget - need) / per_table);
+}
+
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 uint32_t ceil_log2(uint64_t x)
@@ -521,7 +530,7 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     if (!bits_ok(bits) || m < 1 || m > MIH_M_MAX || m > bits) return MIH_ERR_INVALID;
     if ((bits + m - 1) / m > MIH_SUBSTRING_MAX) return MIH_ERR_UNSUPPORTED;
     if (n > 0xFFFFFFFEull || (n && !codes) || ((uintptr_t)codes & 7) != 0) return MIH_ERR_INVALID;
-    mih_build_opts o = {MIH_TABLE_AUTO, MIH_CODES_AUTO, 0, nullptr};
+    mih_build_opts o = {MIH_TABLE_AUTO, MIH_CODES_AUTO, 0, nullptr, 0};
     if (opts) o = *opts;
     if (o.bit_order) {
         // a permutation of 0 .. bits-1
@@ -531,10 +540,11 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
             seen[o.bit_order[p]] = 1;
         }
     }
-    if (o.table_mode > MIH_TABLE_HEADS || o.codes_mode > MIH_CODES_INDIRECT) return MIH_ERR_INVALID;
+    if (o.table_mode > MIH_TABLE_HEADS || o.codes_mode > MIH_CODES_MIXED) return MIH_ERR_INVALID;
+    if (o.codes_mode == MIH_CODES_MIXED && (o.inline_tables < 1 || o.inline_tables >= m)) return MIH_ERR_INVALID;
     // GROUPED tables scan, and HEADS tables read, the codes in table order
     if ((o.table_mode == MIH_TABLE_GROUPED || o.table_mode == MIH_TABLE_HEADS) &&
-        o.codes_mode == MIH_CODES_INDIRECT)
+        (o.codes_mode == MIH_CODES_INDIRECT || o.codes_mode == MIH_CODES_MIXED))
         return MIH_ERR_INVALID;
     if (o.table_mode == MIH_TABLE_HEADS && bits != 64) return MIH_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
@@ -574,7 +584,7 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
         max_entries = std::max<uint64_t>(max_entries, (1ull << ix->len[j]) + 1);
     }
     const uint64_t ids_bytes = (uint64_t)m * n * 4;
-    const uint64_t inline_bytes = (uint64_t)m * n * 8 * W;
+    const uint64_t table_inline_bytes = n * 8 * W;   // one table's copy of the codes
     const uint64_t temp_bytes = 3 * n * 4 + mih::radix_tmp_words(n) * 4 +
                                 mih::scan_tmp_words(max_entries) * 4 + (1 << 20);
     uint64_t budget = o.mem_budget_bytes;
@@ -589,7 +599,15 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     else if (o.table_mode == MIH_TABLE_SORTED) ix->table_mode = MIH_TABLE_SORTED;
     else if (o.table_mode == MIH_TABLE_GROUPED) ix->table_mode = MIH_TABLE_GROUPED;
     else if (o.table_mode == MIH_TABLE_HEADS) ix->table_mode = MIH_TABLE_HEADS;
-    else ix->table_mode = need + direct_bytes <= budget ? MIH_TABLE_DIRECT : MIH_TABLE_SORTED;
+    else if (need + direct_bytes > budget) ix->table_mode = MIH_TABLE_SORTED;
+    else {
+        // DIRECT unless it would leave fewer tables room for inline codes
+        // than SORTED would (their offsets take 2^s words per table)
+        const uint32_t kd = inline_tables_fit(need + direct_bytes, budget, table_inline_bytes, m);
+        const uint32_t ks = inline_tables_fit(need + sorted_bytes, budget, table_inline_bytes, m);
+        ix->table_mode = (o.codes_mode == MIH_CODES_AUTO && kd < m && ks > kd) ? MIH_TABLE_SORTED
+                                                                               : MIH_TABLE_DIRECT;
+    }
     need += ix->table_mode == MIH_TABLE_DIRECT ? direct_bytes
           : ix->table_mode == MIH_TABLE_SORTED ? sorted_bytes
           : ix->table_mode == MIH_TABLE_GROUPED ? grouped_bytes : heads_bytes;
@@ -599,10 +617,13 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     need += build_off_bytes;
     if (o.codes_mode == MIH_CODES_INLINE || ix->table_mode == MIH_TABLE_GROUPED ||
         ix->table_mode == MIH_TABLE_HEADS)
-        ix->codes_mode = MIH_CODES_INLINE;
-    else if (o.codes_mode == MIH_CODES_INDIRECT) ix->codes_mode = MIH_CODES_INDIRECT;
-    else ix->codes_mode = need + inline_bytes <= budget ? MIH_CODES_INLINE : MIH_CODES_INDIRECT;
-    if (ix->codes_mode == MIH_CODES_INLINE) need += inline_bytes;
+        ix->inline_tables = m;
+    else if (o.codes_mode == MIH_CODES_INDIRECT) ix->inline_tables = 0;
+    else if (o.codes_mode == MIH_CODES_MIXED) ix->inline_tables = o.inline_tables;
+    else ix->inline_tables = inline_tables_fit(need, budget, table_inline_bytes, m);
+    ix->codes_mode = ix->inline_tables == m ? MIH_CODES_INLINE
+                   : ix->inline_tables == 0 ? MIH_CODES_INDIRECT : MIH_CODES_MIXED;
+    need += (uint64_t)ix->inline_tables * table_inline_bytes;
     if (o.mem_budget_bytes && need - reserve > budget) { delete ix; return MIH_ERR_NOMEM; }
 
     mih_status st = MIH_OK;
@@ -682,7 +703,7 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
                 T.dir = dir;
             }
             if (e != hipSuccess) { st = from_hip(e); break; }
-            if (ix->codes_mode == MIH_CODES_INLINE) {
+            if (j < ix->inline_tables) {
                 uint64_t *tc = nullptr;
                 if ((e = ix->alloc((void **)&tc, n * 8 * W)) != hipSuccess) { st = from_hip(e); break; }
                 if ((e = mih::gather_codes(codes, ids, n, W, tc, s)) != hipSuccess) { st = from_hip(e); break; }
@@ -922,6 +943,7 @@ mih_status mih_index_get_info(const mih_index *idx, mih_index_info *info)
     info->m = idx->m;
     info->table_mode = idx->table_mode;
     info->codes_mode = idx->codes_mode;
+    info->inline_tables = idx->inline_tables;
     for (uint32_t j = 0; j < idx->m; ++j) {
         info->sub_len[j] = idx->len[j];
         info->sub_start[j] = idx->start[j];

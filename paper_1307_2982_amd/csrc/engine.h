@@ -50,6 +50,7 @@ struct mih_index {
     uint64_t n = 0;
     uint32_t bits = 0, W = 0, m = 0;
     uint32_t table_mode = 0, codes_mode = 0;
+    uint32_t inline_tables = 0;   // tables 0 .. inline_tables - 1 keep inline codes
     uint32_t len[MIH_M_MAX] = {}, start[MIH_M_MAX] = {}, dir_bits[MIH_M_MAX] = {};
     uint16_t bit_order[256] = {};
     uint32_t t_all = 0;

@@ -181,6 +181,9 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
     const uint32_t m = A.m;
     const uint32_t rp = t / m, a = t - rp * m;
     const TableDev T = A.tables[a];
+    // codes in table order: every table of an INLINE index, the leading
+    // tables of a MIXED one (whose kernels are the indirect ones)
+    const bool tinl = INLINE || T.codes != nullptr;
     uint64_t g[W];
     (void)query_key<W>(A, q, a, g);
     uint32_t tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
@@ -310,14 +313,14 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
                 live[u] = e < TC;
                 pos[u] = live[u] ? stage_pos[bl[u]] + (e - stage_cum[bl[u]]) : 0u;
                 id[u] = 0;
-                if (!INLINE && live[u]) id[u] = T.ids[pos[u]];
+                if (!tinl && live[u]) id[u] = T.ids[pos[u]];
             }
 #pragma unroll
             for (int u = 0; u < kWalk; ++u) {
                 if (live[u]) {
                     if (TM == mih::TM_HEADS && e0 + u * MIH_WAVE + lane == stage_cum[bl[u]]) {
                         code[u][0] = stage_code[bl[u]];   // a bucket's first code came with its offsets
-                    } else if (INLINE) {
+                    } else if (tinl) {
                         load_code<W>(T.codes + (uint64_t)pos[u] * W, code[u]);
                     } else {
                         load_code<W>(A.codes + (uint64_t)id[u] * W, code[u]);
@@ -350,7 +353,7 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
                     if (fb && lane == 0) atomicAdd(A.uniq + q, (uint32_t)__popcll(fb));
                 }
                 const bool keep = first && d <= tau;
-                if (keep && INLINE) id[u] = T.ids[pos[u]];
+                if (keep && tinl) id[u] = T.ids[pos[u]];
                 append_candidates(A.qb, q, keep, d, id[u]);
                 if (__ballot(keep)) tau = tighten_tau(A.qb, q, tau);
             }
@@ -539,6 +542,7 @@ __device__ void sweep_item(const mih::MihArgs &A, const mih::Group &G, uint32_t 
     const uint32_t lane = lane_id();
     const uint32_t t = G.t, rp = t / A.m, a = t - rp * A.m;
     const TableDev T = A.tables[a];
+    const bool tinl = INLINE || T.codes != nullptr;   // this table's codes in table order
     const uint32_t L = G.sweep_bits;
     const uint32_t low = L >= 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
     const uint32_t i0 = c * mih::kSweepQueries;
@@ -648,7 +652,7 @@ __device__ void sweep_item(const mih::MihArgs &A, const mih::Group &G, uint32_t 
                 uint32_t id = 0;
 #pragma unroll
                 for (int w = 0; w < W; ++w) g[w] = S.qg[k][w];
-                if (INLINE) {
+                if (tinl) {
                     load_code<W>(T.codes + (uint64_t)pos * W, code);
                 } else {
                     id = T.ids[pos];
@@ -667,7 +671,7 @@ __device__ void sweep_item(const mih::MihArgs &A, const mih::Group &G, uint32_t 
                     }
                 }
                 if (keep) {
-                    if (INLINE) id = T.ids[pos];
+                    if (tinl) id = T.ids[pos];
                     const uint32_t q = S.qslot[k];
                     const uint32_t slot = atomicAdd(&A.qb.count[q], 1u);
                     if (slot < A.qb.cap[q]) A.qb.buf[A.qb.buf_off[q] + slot] = ((uint64_t)d << 32) | id;

@@ -3,7 +3,8 @@
 Each case draws a code length, database size and kind (uniform, clustered,
 or a small pool of codes repeated many times, so that distances tie and
 buckets overflow), a number of substrings, table and codes modes, a launch
-tuning (probes per lane, chunk, occupancy filter, sweep, lookahead), queries
+tuning (probes per lane, chunk, occupancy filter, sweep, lookahead), inline,
+indirect or mixed candidate codes, queries
 that include exact copies and near copies of database codes, per-query k
 (k = 0 and k > n among them) and an r-neighbour radius.  Every kNN row (of
 the multi-index search and of the linear scan) and every r-neighbour list
@@ -38,7 +39,10 @@ def draw(rng):
     smax = 32 if tmode == "sorted" else 24
     m_lo = -(-bits // smax)
     m = int(rng.integers(m_lo, min(m_lo + 6, 64) + 1))
-    cmode = "inline" if tmode in ("grouped", "heads") else str(rng.choice(["inline", "indirect"]))
+    cmode = "inline" if tmode in ("grouped", "heads") else str(rng.choice(["inline", "indirect", "mixed"]))
+    inline_tables = int(rng.integers(1, m)) if cmode == "mixed" and m > 1 else 0
+    if cmode == "mixed" and m == 1:
+        cmode = "inline"
     n = int(rng.choice([1, 2, 3, 17, 257, 4097, 20_000, 60_000]))
     nq = int(rng.integers(1, 41))
     kind = str(rng.choice(["uniform", "clustered", "pool"]))
@@ -46,7 +50,8 @@ def draw(rng):
     tuning = dict(probes_per_lane=J, chunk=64 * J * int(rng.choice([1, 2, 8])), blocks_per_cu=0,
                   occupancy_filter=int(rng.integers(0, 2)), sweep_shift=int(rng.choice([0, 0, 9])),
                   sweep_bits=18, lookahead=int(rng.choice([1, 3, 16, 32])))
-    return dict(bits=bits, W=W, m=m, tmode=tmode, cmode=cmode, n=n, nq=nq, kind=kind, tuning=tuning)
+    return dict(bits=bits, W=W, m=m, tmode=tmode, cmode=cmode, inline_tables=inline_tables, n=n, nq=nq,
+                kind=kind, tuning=tuning)
 
 
 def make_data(rng, c, case):
@@ -82,7 +87,8 @@ def test_random_configuration(mih, case):
     codes, queries, ks = make_data(rng, c, case)
     what = f"case {case}: {c}"
     print(what, flush=True)
-    idx = mih.build(to_dev(codes), c["m"], table_mode=c["tmode"], codes_mode=c["cmode"])
+    idx = mih.build(to_dev(codes), c["m"], table_mode=c["tmode"], codes_mode=c["cmode"],
+                    inline_tables=c["inline_tables"])
     idx.set_tuning(**c["tuning"])
     dq = to_dev(queries)
     ids, dists = idx.knn(dq, ks.tolist())
