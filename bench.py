@@ -120,7 +120,7 @@ def to_device(codes: np.ndarray, chunk_rows: int = 1 << 24):
     return dev
 
 
-def counter_traffic(counters_file, tuning):
+def counter_traffic(counters_file, tuning, modes):
     """HBM bytes per launch of the search kernel from committed rocprofv3
     counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a
     plain copy of known size), or None when the kernel source or the launch
@@ -137,6 +137,8 @@ def counter_traffic(counters_file, tuning):
     if h.hexdigest()[:16] != rec["source_sha256_16"]:
         return None, rec
     if any(tuning.get(k) != v for k, v in rec.get("tuning", {}).items()):
+        return None, rec
+    if tuple(rec.get("modes", ())) != tuple(modes):   # the table and codes modes of the counter runs
         return None, rec
     cal = rec["copy_calibration"]
     fetch = np.mean(rec["fetch_kib_per_launch"]) * cal["fetch_factor"]
@@ -382,9 +384,9 @@ def main():
     achieved = alg_bytes / (kern_ms / 1e3) / 1e9 if kern_ms > 0 else 0.0
     traffic = None
     lines = None
-    if (n, bits, m, nq, tuple(ks)) == (1_000_000_000, 64, 2, 10_000, (100,)) and \
-            (info["table_mode"], info["codes_mode"]) == ("direct", "inline"):
-        traffic, rec = counter_traffic("mih_round_kernel_1e9x64_m2_k100_counters.json", idx.get_tuning())
+    if (n, bits, m, nq, tuple(ks)) == (1_000_000_000, 64, 2, 10_000, (100,)):
+        traffic, rec = counter_traffic("mih_round_kernel_1e9x64_m2_k100_counters.json", idx.get_tuning(),
+                                       (info["table_mode"], info["codes_mode"]))
         if traffic is not None:
             # the reads are random 64 B lines, which FETCH_SIZE counts in full
             per_launch = float(np.mean(rec["fetch_kib_per_launch"])) * 1024 / 64

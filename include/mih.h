@@ -61,17 +61,21 @@ typedef enum mih_status {
  * GROUPED: like the 32-bucket groups of Section 6, one 64-bit record per 32
  * consecutive values (their occupancy bits and the table position of the
  * group's first code, 2^s / 4 bytes per table), and a bucket is found by
- * scanning its group's codes, so GROUPED needs INLINE codes.  AUTO: DIRECT
- * when it fits the memory budget, else SORTED. */
+ * scanning its group's codes, so GROUPED needs INLINE codes.  AUTO: for
+ * 64-bit codes whose tables hold at most one code per bucket on average
+ * (n <= 2^s for the shortest substring), HEADS with INLINE codes when it
+ * fits the memory budget; otherwise DIRECT when it fits, else SORTED (and
+ * see the codes modes). */
 typedef enum mih_table_mode {
     MIH_TABLE_AUTO = 0,
     MIH_TABLE_DIRECT = 1,
     MIH_TABLE_SORTED = 2,
     MIH_TABLE_GROUPED = 3,
-    MIH_TABLE_HEADS = 4      /* 64-bit codes: DIRECT whose offsets sit beside each
-                                bucket's first code in 16-byte entries (2^s + 1
-                                of them per table), so that a one-code bucket
-                                costs one line; needs INLINE codes */
+    MIH_TABLE_HEADS = 4      /* 64-bit codes: DIRECT whose offset and size sit
+                                beside each bucket's first code in 16-byte
+                                entries (2^s + 1 of them per table), so that a
+                                one-code bucket costs one line; needs INLINE
+                                codes */
 } mih_table_mode;
 
 /* Where candidate codes are read during verification.  INLINE: each table
@@ -142,7 +146,8 @@ typedef struct mih_table_view {
                                     with value >= 32g; else NULL            */
     const uint64_t *heads;       /* HEADS: [2^len + 1] pairs of words: the
                                     bucket's first code (0 if empty), then its
-                                    offset in the low 32 bits; else NULL    */
+                                    offset in the low 32 bits and its size in
+                                    the high 32 bits; else NULL             */
 } mih_table_view;
 
 /* Per-call counters of the multi-index search (sums over the queries). */

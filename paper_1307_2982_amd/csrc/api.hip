@@ -599,6 +599,12 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     else if (o.table_mode == MIH_TABLE_SORTED) ix->table_mode = MIH_TABLE_SORTED;
     else if (o.table_mode == MIH_TABLE_GROUPED) ix->table_mode = MIH_TABLE_GROUPED;
     else if (o.table_mode == MIH_TABLE_HEADS) ix->table_mode = MIH_TABLE_HEADS;
+    else if (bits == 64 && (o.codes_mode == MIH_CODES_AUTO || o.codes_mode == MIH_CODES_INLINE) &&
+             n <= (1ull << ix->len[m - 1]) &&
+             need + heads_bytes + (max_entries + 1) * 4 + (uint64_t)m * table_inline_bytes <= budget)
+        // 64-bit codes in sparse tables (at most one code per bucket on
+        // average): a bucket's offset, size and first code in one entry
+        ix->table_mode = MIH_TABLE_HEADS;
     else if (need + direct_bytes > budget) ix->table_mode = MIH_TABLE_SORTED;
     else {
         // DIRECT unless it would leave fewer tables room for inline codes
@@ -735,7 +741,8 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     // the occupancy map pays off where the offsets array outgrows the caches
     uint32_t max_len = 0;
     for (uint32_t j = 0; j < m; ++j) max_len = std::max(max_len, ix->len[j]);
-    ix->tuning.occupancy_filter = (ix->table_mode == MIH_TABLE_DIRECT && max_len >= 26) ? 1u : 0u;
+    ix->tuning.occupancy_filter =
+        ((ix->table_mode == MIH_TABLE_DIRECT || ix->table_mode == MIH_TABLE_HEADS) && max_len >= 26) ? 1u : 0u;
     ix->build_ms = ms_since(t0);
     *out = ix;
     return MIH_OK;
@@ -1123,7 +1130,8 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
     // the grid: (filter, J, chunk) with whole steps, then partition-major
     // sweeps of the large steps with the occupancy filter if there is one
     std::vector<mih_tuning> grid;
-    const uint32_t filters = idx->table_mode == MIH_TABLE_DIRECT ? 2 : 1;
+    const uint32_t filters =
+        (idx->table_mode == MIH_TABLE_DIRECT || idx->table_mode == MIH_TABLE_HEADS) ? 2 : 1;
     for (uint32_t f = 0; f < filters; ++f)
         for (uint32_t J : {4u, 8u, 16u})
             for (uint32_t mult : {2u, 8u, 32u, 128u}) {

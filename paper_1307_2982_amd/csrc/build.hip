@@ -161,10 +161,11 @@ __global__ __launch_bounds__(MIH_BLOCK) void bucket_heads_kernel(const uint32_t 
     const uint64_t stride = (uint64_t)gridDim.x * MIH_BLOCK;
     for (; v <= nbuckets; v += stride) {
         const uint32_t b0 = off[v];
+        const uint32_t c = v < nbuckets ? off[v + 1] - b0 : 0u;
         BucketHead h;
-        h.code = (v < nbuckets && off[v + 1] > b0) ? codes[b0] : 0ull;
+        h.code = c ? codes[b0] : 0ull;
         h.start = b0;
-        h.pad = 0;
+        h.count = c;
         head[v] = h;
     }
 }

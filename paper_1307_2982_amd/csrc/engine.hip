@@ -195,7 +195,10 @@ void Engine::fill_args(MihArgs &A) const
     A.inline_codes = ix_->codes_mode == MIH_CODES_INLINE;
     A.chunk = ix_->tuning.chunk;
     A.J = ix_->tuning.probes_per_lane;
-    A.occ_filter = ix_->tuning.occupancy_filter && ix_->table_mode == MIH_TABLE_DIRECT;
+    // DIRECT and HEADS tables: test the occupancy map before the bucket
+    // (HEADS entries also say whether a bucket is empty; the map is denser)
+    A.occ_filter = ix_->tuning.occupancy_filter &&
+                   (ix_->table_mode == MIH_TABLE_DIRECT || ix_->table_mode == MIH_TABLE_HEADS);
     // distinct codes are counted in whole-step probing only
     A.sweep_shift = count_unique_ ? 0u : ix_->tuning.sweep_shift;
     A.count_unique = count_unique_ ? 1u : 0u;

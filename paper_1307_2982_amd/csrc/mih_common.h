@@ -205,7 +205,7 @@ __device__ __forceinline__ void block_bitonic_sort(uint64_t *v, uint32_t P)
 struct BucketHead {
     uint64_t code;    // the bucket's first code in table order (0 if empty)
     uint32_t start;   // offset of the bucket: codes with a smaller value
-    uint32_t pad;
+    uint32_t count;   // codes in the bucket
 };
 
 // `count` packed entries moved from entry offset src to entry offset dst.

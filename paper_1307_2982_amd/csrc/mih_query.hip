@@ -218,7 +218,7 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
                     gbase[j] = (uint32_t)(rec >> 32) + __popc(occ & ((1u << bit) - 1u));
                 }
             }
-        } else if (TM == mih::TM_HEADS || (TM == mih::TM_DIRECT && A.occ_filter)) {
+        } else if ((TM == mih::TM_HEADS || TM == mih::TM_DIRECT) && A.occ_filter) {
             occ_bits = 0;
 #pragma unroll
             for (int j = 0; j < J; ++j)
@@ -233,9 +233,9 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
                 if (TM == mih::TM_GROUPED) {
                     group_scan<W>(T, A.n, key, gbase[j], lo[j], cnt[j]);
                 } else if (TM == mih::TM_HEADS) {
-                    const BucketHead h = T.head[key];
+                    const BucketHead h = T.head[key];   // one 16-byte entry, one line
                     lo[j] = h.start;
-                    cnt[j] = T.head[(uint64_t)key + 1].start - h.start;
+                    cnt[j] = h.count;
                     head_code[j] = h.code;
                 } else if (TM == mih::TM_DIRECT) {
                     const uint32_t b0 = T.off[key];
@@ -494,8 +494,9 @@ __device__ __forceinline__ void second_lookup(const TableDev &T, uint64_t n, uin
         if ((pa >> bit) & 1u) group_scan<W>(T, n, key, pb + __popc(pa & ((1u << bit) - 1u)), lo, cnt);
     } else if (TM == mih::TM_HEADS) {
         if ((pa >> (key & 31)) & 1u) {
-            lo = T.head[key].start;
-            cnt = T.head[(uint64_t)key + 1].start - lo;
+            const BucketHead h = T.head[key];
+            lo = h.start;
+            cnt = h.count;
         }
     } else if (TM == mih::TM_DIRECT) {
         if (occ_filter) {

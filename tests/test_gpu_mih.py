@@ -116,8 +116,8 @@ def test_mih_launch_tunings_agree(mih, tmode, occ, shift):
 
 
 def test_heads_tables_match_algorithm1(mih):
-    # HEADS (64-bit codes): entry v holds the offset of bucket v and, for a
-    # non-empty bucket, its first code in (value, id) order
+    # HEADS (64-bit codes): entry v holds the offset and size of bucket v
+    # and, for a non-empty bucket, its first code in (value, id) order
     n = 40_003
     codes = datagen.uniform_codes(n, 64, 302)
     ref = oracle.MihCpu(codes, 3)
@@ -130,6 +130,8 @@ def test_heads_tables_match_algorithm1(mih):
         nb = 1 << tab["len"]
         start = np.searchsorted(values, np.arange(nb + 1, dtype=np.uint64)).astype(np.int64)
         assert np.array_equal(heads[:, 1] & 0xFFFFFFFF, start)
+        size = np.append(start[1:] - start[:-1], 0)
+        assert np.array_equal(heads[:, 1] >> 32, size)
         nonempty = start[1:] > start[:-1]
         first = np.zeros(nb, dtype=np.uint64)
         first[nonempty] = codes[ids[start[:-1][nonempty]], 0]
