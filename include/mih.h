@@ -326,8 +326,10 @@ typedef struct mih_tuning {
 #define MIH_LOOKAHEAD_DEFAULT 16u
 
 /* Current tuning of an index (defaults after mih_build: 4, 8192, 0, the
- * occupancy filter on for DIRECT tables of substrings of 26 bits or more,
- * sweep off, 18 sweep bits, lookahead MIH_LOOKAHEAD_DEFAULT). */
+ * occupancy filter on for DIRECT and HEADS tables of substrings of 26 bits
+ * or more, sweep off, 18 sweep bits, lookahead MIH_LOOKAHEAD_DEFAULT; HEADS
+ * tables of substrings of 26 bits or more start at 8 probes per lane and
+ * chunk 16384). */
 mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
 
 /* Replace the tuning; MIH_ERR_INVALID (index unchanged) if a field is out of

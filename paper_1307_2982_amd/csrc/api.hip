@@ -743,6 +743,12 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     for (uint32_t j = 0; j < m; ++j) max_len = std::max(max_len, ix->len[j]);
     ix->tuning.occupancy_filter =
         ((ix->table_mode == MIH_TABLE_DIRECT || ix->table_mode == MIH_TABLE_HEADS) && max_len >= 26) ? 1u : 0u;
+    if (ix->table_mode == MIH_TABLE_HEADS && max_len >= 26) {
+        // one entry read per occupied probe leaves registers for more
+        // probes in flight per lane (the autotuner's usual pick there)
+        ix->tuning.probes_per_lane = 8;
+        ix->tuning.chunk = 16384;
+    }
     ix->build_ms = ms_since(t0);
     *out = ix;
     return MIH_OK;
