@@ -123,9 +123,9 @@ def to_device(codes: np.ndarray, chunk_rows: int = 1 << 24):
 def counter_traffic(counters_file, tuning, modes):
     """HBM bytes per launch of the search kernel from committed rocprofv3
     counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a
-    plain copy of known size), or None when the kernel source or the launch
-    tuning has changed since the counters were taken or no counters exist
-    for this workload."""
+    plain copy of known size), or None when the kernel source, the launch
+    tuning or the table and codes modes differ from those of the counter
+    runs, or no counters exist for this workload."""
     import hashlib
     path = os.path.join(ROOT, "profiles", counters_file)
     if not os.path.exists(path):
