@@ -18,12 +18,16 @@ Contents:
   of Section 7.
 * ``substrings``: the substring optimisation of Section 5.4 (bit
   co-occurrence counts and the greedy bit order).
+* ``first_encounter``: which codes Algorithm 3 has met after each step, from
+  the substring distances (brute force); the reference of the early stops
+  of Section 7.
 * ``formulas``: the paper's closed forms (Eq. 1, 5, 6, 7, the memory formula
   of Section 6 and the q / log2 n heuristic of Section 3.1).
 
 Parity status: the kNN oracle is pinned by the Python brute force, by closed
 forms and by library routines (numpy popcount + lexsort); MIH-CPU is pinned
-by agreement with the oracle for every m.
+by agreement with the oracle for every m, and its early stops by agreement
+with ``first_encounter`` (answers and step counts).
 """
 from __future__ import annotations
 
@@ -33,6 +37,7 @@ import subprocess
 
 import numpy as np
 
+from . import first_encounter  # noqa: F401
 from . import formulas  # noqa: F401
 from .brute import knn_brute, rnn_brute  # noqa: F401
 
@@ -214,10 +219,12 @@ class MihCpu:
         stats = {f: getattr(st, f) for f, _ in _Stats._fields_}
         return ids[:k].copy(), dists[:k].copy(), stats
 
-    def knn_approx(self, query, k: int, max_step: int | None = None, max_found: int = 0):
+    def knn_approx(self, query, k: int, max_step: int | None = None, max_found: int = 0,
+                   stats: bool = False):
         """Algorithm 3 stopped after the step covering radius max_step, or
         after the step in which max_found distinct codes have been met
-        (Section 7); the k best codes met."""
+        (Section 7); the k best codes met (and, with stats, the counters of
+        the search: ``radius`` is the number of steps run)."""
         q = np.ascontiguousarray(query, dtype=np.uint64).reshape(-1)
         ids = np.empty(max(k, 1), dtype=np.uint32)
         dists = np.empty(max(k, 1), dtype=np.uint32)
@@ -227,6 +234,8 @@ class MihCpu:
                                       ids.ctypes.data, dists.ctypes.data, ctypes.byref(st))
         if rc != 0:
             raise MemoryError("MIH-CPU out of memory")
+        if stats:
+            return ids[:k].copy(), dists[:k].copy(), {f: getattr(st, f) for f, _ in _Stats._fields_}
         return ids[:k].copy(), dists[:k].copy()
 
     def rnn(self, query, r: int):
