@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--no-rnn", action="store_true", help="skip the r-neighbour leg")
     ap.add_argument("--no-approx", action="store_true", help="skip the approximate-search leg")
     ap.add_argument("--substring-opt", action="store_true",
-                    help="also time the index built with optimised substrings (Section 5.4)")
+                    help="also time the index built with optimised substrings (Section 5.5)")
     ap.add_argument("--choose-m", action="store_true",
                     help="also pick m by timing candidates on 1000 database rows (Section 6)")
     ap.add_argument("--gather-calib", type=float, default=0.0,
@@ -464,7 +464,7 @@ def main():
 
     subopt = None
     if args.substring_opt:
-        # Section 5.4: the same index with the greedy bit order from a sample
+        # Section 5.5: the same index with the greedy bit order from a sample
         t = time.time()
         sample = min(n, 1_000_000)
         torch.cuda.synchronize()

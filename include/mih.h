@@ -98,7 +98,7 @@ typedef struct mih_build_opts {
     mih_codes_mode codes_mode;
     uint64_t mem_budget_bytes;   /* 0: the device memory free at build time */
     const uint16_t *bit_order;   /* host [bits] or NULL.  Substring optimisation
-                                    (Section 5.4): a permutation of the code bits;
+                                    (Section 5.5): a permutation of the code bits;
                                     substring j is made of the code bits
                                     bit_order[start_j .. start_j + s_j), and bit
                                     k of its key is code bit bit_order[start_j + k].
@@ -395,7 +395,7 @@ mih_status mih_choose_m(const uint64_t *codes, uint64_t n, uint32_t bits, const 
                         const mih_build_opts *opts, void *stream, uint32_t *best_m,
                         mih_m_trial *trials, uint32_t *ntrials);
 
-/* ---- Substring optimisation (Section 5.4) ------------------------------
+/* ---- Substring optimisation (Section 5.5) ------------------------------
  *
  * Co-occurrence counts of the code bits over n sample codes:
  *   device codes  [n][bits/64]
@@ -405,7 +405,7 @@ mih_status mih_choose_m(const uint64_t *codes, uint64_t n, uint32_t bits, const 
 mih_status mih_bit_cooccurrence(const uint64_t *codes, uint64_t n, uint32_t bits, void *stream,
                                 uint32_t *counts);
 
-/* The greedy bit order of Section 5.4, from the counts above (host only).
+/* The greedy bit order of Section 5.5, from the counts above (host only).
  * With |Pearson correlation| between bits taken from the counts (0 for a
  * constant bit): substring 0 starts with first_bit; substring j starts with
  * the unused bit most correlated with the first bit of substring j - 1; then

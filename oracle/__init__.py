@@ -16,7 +16,7 @@ Contents:
   test subject used to check the reading of the algorithm; with early
   stopping (``knn_approx``) it is the reference of the approximate variants
   of Section 7.
-* ``substrings``: the substring optimisation of Section 5.4 (bit
+* ``substrings``: the substring optimisation of Section 5.5 (bit
   co-occurrence counts and the greedy bit order).
 * ``first_encounter``: which codes Algorithm 3 has met after each step, from
   the substring distances (brute force); the reference of the early stops

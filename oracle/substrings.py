@@ -1,4 +1,4 @@
-"""Substring optimisation of Section 5.4, written out (test infrastructure).
+"""Substring optimisation of Section 5.5, written out (test infrastructure).
 
 TEST INFRASTRUCTURE ONLY: imported by the tests alone.  Shares no code with
 the GPU library.

@@ -384,7 +384,7 @@ class Index:
 def build(codes: torch.Tensor, m: int, table_mode: str = "auto", codes_mode: str = "auto",
           mem_budget_bytes: int = 0, bit_order=None, inline_tables: int = 0) -> Index:
     """Build the m substring tables (Algorithm 1) on the device; bit_order
-    (a permutation of the code bits, Section 5.4) places the substrings;
+    (a permutation of the code bits, Section 5.5) places the substrings;
     codes_mode "mixed" keeps inline codes in the first inline_tables tables."""
     codes = _codes_arg(codes, "codes")
     n, W = codes.shape
@@ -415,7 +415,7 @@ def bit_cooccurrence(codes: torch.Tensor):
 
 
 def greedy_bit_order(counts, n: int, m: int, first_bit: int = 0):
-    """The Section 5.4 greedy bit order from co-occurrence counts of n codes."""
+    """The Section 5.5 greedy bit order from co-occurrence counts of n codes."""
     import numpy as np
     counts = np.ascontiguousarray(counts, dtype=np.uint32)
     bits = counts.shape[0]

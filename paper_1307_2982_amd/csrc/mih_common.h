@@ -245,7 +245,7 @@ __device__ __forceinline__ uint64_t code_word(const uint64_t (&c)[W], uint32_t i
 }
 
 // Key of a code in table T: its substring bits, contiguous or in the table's
-// bit order (substring optimisation, Section 5.4).
+// bit order (substring optimisation, Section 5.5).
 template <int W>
 __device__ __forceinline__ uint32_t table_key(const uint64_t (&c)[W], const TableDev &T)
 {

@@ -1,4 +1,4 @@
-// Substring optimisation (Section 5.4): assign the code bits to substrings
+// Substring optimisation (Section 5.5): assign the code bits to substrings
 // so that bits within one substring are as little correlated as possible.
 //
 // The correlations come from co-occurrence counts over a sample of codes,

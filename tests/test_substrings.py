@@ -1,4 +1,4 @@
-"""Substring optimisation (Section 5.4): the oracle's greedy against a design
+"""Substring optimisation (Section 5.5): the oracle's greedy against a design
 whose answer follows from the description by hand, its co-occurrence counts
 against brute force, and the library's host-side greedy against the oracle.
 No GPU."""
