@@ -227,6 +227,29 @@ mih_status linscan_knn_ex(const uint64_t *codes, uint64_t n, uint32_t bits,
                           const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
                           void *stream, mih_scan_stats *stats);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): linscan_knn with
+ * every device buffer taken from a fixed array of MIH_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each GPU it has run this call on, from the first
+ * such call until the process ends.  No hipMalloc, hipFree or other
+ * allocating routine is called.  Results are those of linscan_knn.
+ *   Arguments as in linscan_knn; the current device must be the stream's.
+ *   A batch whose buffers do not fit half the array is scanned in slices of
+ *   queries (one pass over the database per slice; a query with k <= 4096
+ *   always fits); the other half takes the exact re-runs of queries whose
+ *   candidate buffer overflowed.
+ * Errors: as linscan_knn; MIH_ERR_CAPACITY (outputs incomplete) when the
+ * exact re-run of a single query does not fit, i.e. when more than about
+ * 16 M codes lie at or within that query's k-th distance.
+ * Every call on one GPU shares that GPU's array and leaves it holding its
+ * last contents: calls that overlap on one GPU (several host threads, or
+ * several streams) race, so the caller serialises them. */
+#define MIH_NOALLOC_SCRATCH_BYTES (256ull << 20)
+mih_status linscan_knn_noalloc(const uint64_t *codes, uint64_t n, uint32_t bits,
+                               const uint64_t *queries, uint32_t nq, uint32_t k,
+                               const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
+                               void *stream);
+
 /* Approximate kNN (Section 7): Algorithm 3 stopped early, returning the k
  * best of the codes met so far.
  *   max_radius      stop after the step that covers this radius, even if

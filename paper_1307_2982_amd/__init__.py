@@ -106,7 +106,8 @@ class RnnView(ctypes.Structure):
                 ("offsets", ctypes.c_void_p), ("ids", ctypes.c_void_p), ("dists", ctypes.c_void_p)]
 
 
-EXPORTED = ["mih_build", "mih_knn", "mih_knn_ex", "linscan_knn", "linscan_knn_ex", "mih_free",
+EXPORTED = ["mih_build", "mih_knn", "mih_knn_ex", "linscan_knn", "linscan_knn_ex", "linscan_knn_noalloc",
+            "mih_free",
             "mih_rnn", "mih_rnn_ex", "linscan_rnn", "mih_rnn_result_view", "mih_rnn_result_free",
             "mih_knn_approx", "mih_model_cost", "mih_model_radius", "mih_choose_m", "mih_bit_cooccurrence",
             "mih_greedy_bit_order",
@@ -143,6 +144,8 @@ def load():
     L.linscan_knn.restype = i32
     L.linscan_knn_ex.argtypes = [vp, u64, u32, vp, u32, u32, vp, vp, vp, vp, ctypes.POINTER(ScanStats)]
     L.linscan_knn_ex.restype = i32
+    L.linscan_knn_noalloc.argtypes = [vp, u64, u32, vp, u32, u32, vp, vp, vp, vp]
+    L.linscan_knn_noalloc.restype = i32
     L.mih_free.argtypes = [vp]
     L.mih_free.restype = None
     L.mih_rnn.argtypes = [vp, vp, u32, u32, vp, vp, ctypes.POINTER(vp)]
@@ -543,6 +546,30 @@ def linscan_knn(codes: torch.Tensor, queries: torch.Tensor, k, stats: bool = Fal
     _check(rc, "linscan_knn")
     ids, dists = _shape(ids, dists, total, nq, kk, kl)
     return (ids, dists, st.as_dict()) if stats else (ids, dists)
+
+
+def linscan_knn_noalloc(codes: torch.Tensor, queries: torch.Tensor, k, out=None):
+    """linscan_knn through the entry point that allocates no device memory
+    (its buffers sit in a fixed array of the library).  ``out``: optional
+    preallocated (ids, dists) int32 tensors of the right size, so that the
+    call itself allocates nothing anywhere."""
+    codes = _codes_arg(codes, "codes")
+    queries = _codes_arg(queries, "queries")
+    if queries.shape[1] != codes.shape[1]:
+        raise ValueError("queries and codes differ in length")
+    n, W = codes.shape
+    nq = queries.shape[0]
+    kk, kt, kl = _k_arg(k, nq, queries.device)
+    if out is None:
+        ids, dists, total = _outputs(nq, kk, kl, queries.device)
+    else:
+        ids, dists = out
+        total = ids.numel()
+    rc = load().linscan_knn_noalloc(codes.data_ptr() if n else None, n, 64 * W, queries.data_ptr(), nq,
+                                    kk, kt.data_ptr() if kt is not None else None, ids.data_ptr(),
+                                    dists.data_ptr(), _stream())
+    _check(rc, "linscan_knn_noalloc")
+    return _shape(ids, dists, total, nq, kk, kl)
 
 
 # ------------------------------------------------------------------ serving

@@ -113,6 +113,30 @@ struct Scratch {
     }
 };
 
+// Device memory of one linear-scan call: allocated per call, or carved from
+// a caller's region (base != nullptr), in which case nothing is allocated and
+// a request that does not fit fails with MIH_ERR_CAPACITY.
+struct Arena {
+    char *base = nullptr;
+    uint64_t size = 0, used = 0;
+    bool fits(uint64_t bytes) const { return used <= size && bytes <= size - used; }
+};
+
+// Memory for `bytes` from the arena (marked used until release) or from a
+// fresh allocation held in `own`.
+mih_status arena_take(Arena *arena, Scratch &own, uint64_t bytes, char *&p)
+{
+    if (arena) {
+        if (!arena->fits(bytes)) return MIH_ERR_CAPACITY;
+        p = arena->base + arena->used;
+        arena->used += bytes;
+        return MIH_OK;
+    }
+    MIH_TRY(own.ensure(bytes));
+    p = (char *)own.ptr;
+    return MIH_OK;
+}
+
 // A pair of HIP events around launches on one stream (disabled unless the
 // caller asked for statistics).
 struct EventPair {
@@ -271,11 +295,39 @@ namespace {
 
 mih_status linscan_batch(const uint64_t *codes, uint64_t n, uint32_t bits, BatchSpec &b,
                          uint32_t *out_ids, uint32_t *out_dists, hipStream_t s, int depth,
-                         mih_scan_stats *stats);
+                         mih_scan_stats *stats, Arena *arena = nullptr);
+
+// Bytes of device memory linscan_batch carves for a batch.
+uint64_t linscan_batch_bytes(const BatchSpec &b, uint32_t bits)
+{
+    const uint32_t W = bits / 64;
+    std::vector<uint64_t> buf_off;
+    const uint64_t words = buffer_words(b, buf_off);
+    BatchBufs B;
+    Carver c0;
+    carve_batch(c0, b, bits, W, words, 1, B);
+    c0.take<uint64_t>((uint64_t)mih::linscan_pad(b.nq) * W);
+    return c0.used;
+}
+
+// The queries of `rb` from position i0 on that fit the arena with one
+// batch (at least one; 0 if not even one fits).
+uint32_t rerun_slice(const BatchSpec &rb, uint32_t i0, uint32_t bits, const Arena &arena)
+{
+    uint32_t lo = 0, hi = rb.nq - i0;   // the largest count that fits, by bisection
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        BatchSpec t;
+        t.nq = mid;
+        t.cap.assign(rb.cap.begin() + i0, rb.cap.begin() + i0 + mid);
+        if (arena.fits(linscan_batch_bytes(t, bits))) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 mih_status rerun_linscan(const uint64_t *codes, uint64_t n, uint32_t bits, const BatchSpec &b,
                          BatchBufs &B, uint32_t *out_ids, uint32_t *out_dists, hipStream_t s,
-                         int depth, mih_scan_stats *stats)
+                         int depth, mih_scan_stats *stats, Arena *arena)
 {
     uint32_t novf = 0;
     MIH_TRY(download(&novf, B.ovf_count, sizeof(uint32_t), s));
@@ -289,9 +341,9 @@ mih_status rerun_linscan(const uint64_t *codes, uint64_t n, uint32_t bits, const
     c0.take<uint32_t>(novf); c0.take<uint32_t>(novf); c0.take<uint32_t>(novf);
     c0.take<uint64_t>((uint64_t)novf * W);
     Scratch tmp;
-    MIH_TRY(tmp.ensure(c0.used));
+    const uint64_t arena_mark = arena ? arena->used : 0;
     Carver c;
-    c.base = (char *)tmp.ptr;
+    MIH_TRY_STATUS(arena_take(arena, tmp, c0.used, c.base));
     uint32_t *dlist = c.take<uint32_t>(novf);
     uint32_t *dtau = c.take<uint32_t>(novf);
     uint32_t *dcap = c.take<uint32_t>(novf);
@@ -315,16 +367,35 @@ mih_status rerun_linscan(const uint64_t *codes, uint64_t n, uint32_t bits, const
             rb.row_off[i] = b.row_off[list[i]];
             if (rb.cap[i] == 0 && rb.k[i]) rb.cap[i] = 1;
         }
-        st = linscan_batch(codes, n, bits, rb, out_ids, out_dists, s, depth + 1, stats);
+        if (!arena) {
+            st = linscan_batch(codes, n, bits, rb, out_ids, out_dists, s, depth + 1, stats);
+            break;
+        }
+        // in a fixed region the re-run goes in slices of queries that fit
+        for (uint32_t i0 = 0; i0 < novf && st == MIH_OK;) {
+            const uint32_t cnt = rerun_slice(rb, i0, bits, *arena);
+            if (cnt == 0) { st = MIH_ERR_CAPACITY; break; }
+            BatchSpec sb;
+            sb.queries = rb.queries + (uint64_t)i0 * W;
+            sb.nq = cnt;
+            sb.tau0 = rb.tau0 + i0;
+            sb.rnn = rb.rnn;
+            sb.cap.assign(rb.cap.begin() + i0, rb.cap.begin() + i0 + cnt);
+            sb.k.assign(rb.k.begin() + i0, rb.k.begin() + i0 + cnt);
+            sb.row_off.assign(rb.row_off.begin() + i0, rb.row_off.begin() + i0 + cnt);
+            st = linscan_batch(codes, n, bits, sb, out_ids, out_dists, s, depth + 1, stats, arena);
+            i0 += cnt;
+        }
     } while (0);
     (void)hipStreamSynchronize(s);
     tmp.release();
+    if (arena) arena->used = arena_mark;
     return st;
 }
 
 mih_status linscan_batch(const uint64_t *codes, uint64_t n, uint32_t bits, BatchSpec &b,
                          uint32_t *out_ids, uint32_t *out_dists, hipStream_t s, int depth,
-                         mih_scan_stats *stats)
+                         mih_scan_stats *stats, Arena *arena)
 {
     if (b.nq == 0) return MIH_OK;
     const uint32_t W = bits / 64;
@@ -332,13 +403,10 @@ mih_status linscan_batch(const uint64_t *codes, uint64_t n, uint32_t bits, Batch
     const uint64_t words = buffer_words(b, buf_off);
     BatchBufs B;
     const uint64_t qrows = mih::linscan_pad(b.nq);
-    Carver c0;
-    carve_batch(c0, b, bits, W, words, 1, B);
-    c0.take<uint64_t>(qrows * W);
     Scratch mem;
-    MIH_TRY(mem.ensure(c0.used));
+    const uint64_t arena_mark = arena ? arena->used : 0;
     Carver c;
-    c.base = (char *)mem.ptr;
+    MIH_TRY_STATUS(arena_take(arena, mem, linscan_batch_bytes(b, bits), c.base));
     carve_batch(c, b, bits, W, words, 1, B);
     uint64_t *qpad = c.take<uint64_t>(qrows * W);
     mih_status st = MIH_OK;
@@ -400,10 +468,11 @@ mih_status linscan_batch(const uint64_t *codes, uint64_t n, uint32_t bits, Batch
             if (download(cnt.data(), B.qb.count, sizeof(uint32_t) * b.nq, s) == hipSuccess)
                 for (uint32_t i = 0; i < b.nq; ++i) stats->appended += cnt[i];
         }
-        st = rerun_linscan(codes, n, bits, b, B, out_ids, out_dists, s, depth, stats);
+        st = rerun_linscan(codes, n, bits, b, B, out_ids, out_dists, s, depth, stats, arena);
     } while (0);
     (void)hipStreamSynchronize(s);
     mem.release();
+    if (arena) arena->used = arena_mark;
     return st;
 }
 
@@ -466,6 +535,67 @@ mih_status check_query_args(uint32_t bits, const uint64_t *queries, uint32_t nq,
 }
 
 }  // namespace
+
+namespace mih {
+
+// linscan_knn with every buffer carved from [base, base + size): slices of
+// queries whose first pass fits in half the region, the other half left to
+// the exact re-runs of overflowed queries.  Allocates no device memory.
+mih_status linscan_check_args(const uint64_t *codes, uint64_t n, uint32_t bits,
+                              const uint64_t *queries, uint32_t nq, uint32_t k,
+                              const uint32_t *k_per_query, const uint32_t *out_ids,
+                              const uint32_t *out_dists)
+{
+    MIH_TRY_STATUS(check_query_args(bits, queries, nq, out_ids, out_dists));
+    if (n > 0xFFFFFFFEull || (n && !codes) || ((uintptr_t)codes & 7) != 0) return MIH_ERR_INVALID;
+    if (!k_per_query && k > MIH_K_MAX) return MIH_ERR_UNSUPPORTED;
+    return MIH_OK;
+}
+
+mih_status linscan_knn_in_region(const uint64_t *codes, uint64_t n, uint32_t bits,
+                                 const uint64_t *queries, uint32_t nq, uint32_t k,
+                                 const uint32_t *k_per_query, uint32_t *out_ids,
+                                 uint32_t *out_dists, hipStream_t s, char *base, uint64_t size)
+{
+    MIH_TRY_STATUS(linscan_check_args(codes, n, bits, queries, nq, k, k_per_query, out_ids, out_dists));
+    if (!base || ((uintptr_t)base & 255) != 0) return MIH_ERR_INVALID;
+    const uint32_t W = bits / 64;
+    BatchSpec all;
+    all.queries = queries;
+    all.nq = nq;
+    MIH_TRY_STATUS(read_k(nq, k, k_per_query, s, all.k));
+    row_offsets(all.k, all.row_off);
+    all.cap.resize(nq);
+    for (uint32_t i = 0; i < nq; ++i) all.cap[i] = scan_cap(all.k[i]);
+    if (n == 0) {
+        const uint64_t total = all.row_off.empty() ? 0 : all.row_off.back() + all.k.back();
+        MIH_TRY(mih::fill_u32(out_ids, total, MIH_SENTINEL, s));
+        MIH_TRY(mih::fill_u32(out_dists, total, MIH_SENTINEL, s));
+        MIH_TRY(hipStreamSynchronize(s));
+        return MIH_OK;
+    }
+    Arena first;   // the half of the region a slice's first pass may use
+    first.base = base;
+    first.size = size / 2 / 256 * 256;
+    for (uint32_t i0 = 0; i0 < nq;) {
+        const uint32_t cnt = rerun_slice(all, i0, bits, first);
+        if (cnt == 0) return MIH_ERR_CAPACITY;
+        BatchSpec b;
+        b.queries = queries + (uint64_t)i0 * W;
+        b.nq = cnt;
+        b.k.assign(all.k.begin() + i0, all.k.begin() + i0 + cnt);
+        b.row_off.assign(all.row_off.begin() + i0, all.row_off.begin() + i0 + cnt);
+        b.cap.assign(all.cap.begin() + i0, all.cap.begin() + i0 + cnt);
+        Arena whole;
+        whole.base = base;
+        whole.size = size;
+        MIH_TRY_STATUS(linscan_batch(codes, n, bits, b, out_ids, out_dists, s, 0, nullptr, &whole));
+        i0 += cnt;
+    }
+    return MIH_OK;
+}
+
+}  // namespace mih
 
 // ============================================================== C ABI
 

@@ -327,6 +327,18 @@ hipError_t linscan_init(const LinscanArgs &a, uint64_t sample, const uint32_t *t
                         hipStream_t s);
 hipError_t linscan_run(const LinscanArgs &a, uint32_t num_cus, hipStream_t s);
 
+// api.hip: linscan_knn with every device buffer carved from the region
+// [base, base + size) (256-byte aligned); allocates no device memory.
+// MIH_ERR_CAPACITY when one query's pass or exact re-run does not fit.
+mih_status linscan_check_args(const uint64_t *codes, uint64_t n, uint32_t bits,
+                              const uint64_t *queries, uint32_t nq, uint32_t k,
+                              const uint32_t *k_per_query, const uint32_t *out_ids,
+                              const uint32_t *out_dists);
+mih_status linscan_knn_in_region(const uint64_t *codes, uint64_t n, uint32_t bits,
+                                 const uint64_t *queries, uint32_t nq, uint32_t k,
+                                 const uint32_t *k_per_query, uint32_t *out_ids,
+                                 uint32_t *out_dists, hipStream_t s, char *base, uint64_t size);
+
 // topk.hip
 struct FinalArgs {
     QueryBatch qb;

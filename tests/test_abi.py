@@ -54,6 +54,8 @@ def test_argument_errors_need_no_device():
     assert lib.linscan_rnn(None, 0, 96, None, 0, 3, None, None, ctypes.byref(h)) == 1   # bad bits
     assert lib.linscan_rnn(None, 0, 64, None, 2, 3, None, None, ctypes.byref(h)) == 1   # queries NULL
     assert lib.linscan_rnn(None, 0, 64, None, 0, 3, None, None, None) == 1        # out NULL
+    assert lib.linscan_knn_noalloc(None, 0, 64, None, 1, 5, None, None, None, None) == 1   # queries NULL
+    assert lib.linscan_knn_noalloc(None, 0, 96, None, 0, 5, None, None, None, None) == 1   # bad bits
     assert lib.mih_rnn_result_view(None, None) == 1
     lib.mih_rnn_result_free(None)                                                 # ignored
 
