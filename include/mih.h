@@ -343,6 +343,31 @@ typedef struct mih_tuning {
                                   and its shell masks in four passes of
                                   them.  Exact searches only: approximate
                                   ones (mih_knn_approx) always use 1        */
+    uint32_t sweep_queries;    /* swept steps on tables with an occupancy map
+                                  (DIRECT with the filter, HEADS): queries
+                                  per work item, a multiple of 64 in
+                                  64..4096; the partitions there have
+                                  2^min(sweep_bits, 18) values, whose
+                                  occupancy bits a workgroup keeps in LDS   */
+    uint32_t buffer_mult;      /* candidate-buffer entries per kNN query:
+                                  buffer_mult * max(k, 256), 1..64.  Fewer
+                                  entries admit more queries at once; a query
+                                  whose buffer overflows is re-run with an
+                                  exact capacity (same result, more time)   */
+    uint32_t small_batch;      /* exact batches of at most this many queries
+                                  (0..65536) whose expected work per query
+                                  is small run in one launch: a workgroup
+                                  per query takes every step and writes the
+                                  top-k rows, with no host round trip      */
+    uint32_t round_masks;      /* work quantum: the most shell masks one query
+                                  probes in one device round (0: no limit); a
+                                  larger step is continued over several
+                                  rounds, so that the rounds of a serving
+                                  loop stay short and requests that arrive
+                                  meanwhile do not wait for a whole large
+                                  step of the others.  Rounded up to whole
+                                  work items (chunk); steps are then never
+                                  swept */
 } mih_tuning;
 
 #define MIH_LOOKAHEAD_MAX 32u
@@ -350,9 +375,10 @@ typedef struct mih_tuning {
 
 /* Current tuning of an index (defaults after mih_build: 4, 8192, 0, the
  * occupancy filter on for DIRECT and HEADS tables of substrings of 26 bits
- * or more, sweep off, 18 sweep bits, lookahead MIH_LOOKAHEAD_DEFAULT; HEADS
- * tables of substrings of 26 bits or more start at 8 probes per lane and
- * chunk 16384). */
+ * or more, sweep off, 18 sweep bits, lookahead MIH_LOOKAHEAD_DEFAULT, 256
+ * sweep queries, buffer_mult 8, small_batch 512, round_masks 0; HEADS tables
+ * of substrings of 26 bits or more start at 4 probes per lane, chunk 8192
+ * and sweeps with sweep_shift 3, 17 sweep bits and 4096 sweep queries). */
 mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
 
 /* Replace the tuning; MIH_ERR_INVALID (index unchanged) if a field is out of
@@ -361,11 +387,13 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning);
 
 /* Time mih_knn over a grid of tunings (probes_per_lane 4, 8, 16; chunk of
  * 2, 8, 32 or 128 times 64 * probes_per_lane; all workgroups that fit; with and
- * without the occupancy filter on DIRECT tables; and, for substrings of 20
- * bits or more, sweeps with sweep_shift 3 and 18 or 20 sweep bits; the
- * lookahead of the current tuning) on the given sample of queries, time the
- * three fastest twice more, keep the fastest in the index and write it to
- * *chosen (may be NULL).  Results do not depend on the tuning, so the
+ * without the occupancy filter on DIRECT and HEADS tables; and, for
+ * substrings of 20 bits or more, sweeps with sweep_shift 3: on tables with
+ * an occupancy map 17 or 18 sweep bits and 4096 sweep queries, otherwise 18
+ * or 20 sweep bits; the lookahead of the current tuning) on
+ * the given sample of queries, time the three fastest twice more, then the
+ * fastest with buffer_mult 4 and 16 twice each; keep the fastest in the
+ * index and write it to *chosen (may be NULL).  Results do not depend on the tuning, so the
  * sample only has to look like the real queries (how far rounds run ahead
  * depends on the batch size: a sample as large as the real batches tunes
  * best).  Arguments as mih_knn. */
@@ -500,6 +528,20 @@ mih_status mih_server_get_stats(mih_server *srv, mih_server_stats *stats);
 
 /* Release a server (pending and in-flight requests are dropped). */
 void mih_server_destroy(mih_server *srv);
+
+/* Measurement helper (not part of the search): the device's rate of
+ * independent random 64-byte line reads, the kind of read the multi-index
+ * search is made of, so that its fetched lines per second can be put beside
+ * a ceiling.  Reads about `reads` 8-byte words, each from a pseudo-random
+ * line of device array[words] (words >= 8, 8-byte aligned), every lane
+ * keeping `depth` (1, 4, 8 or 16) loads in flight; the words read are
+ * summed into device *sink (one 8-byte word) so that no load is dropped.
+ * The lanes take a whole number of rounds of `depth` reads, so slightly more
+ * than `reads` may be read: 256 x 8 x 256 lanes on 256 CUs.
+ * *ms (host) receives the kernel time.  Errors: MIH_ERR_INVALID for NULL
+ * pointers, words < 8, reads = 0 or another depth. */
+mih_status mih_random_read_rate(const uint64_t *array, uint64_t words, uint64_t reads, uint32_t depth,
+                                uint64_t *sink, void *stream, double *ms);
 
 /* Fill *info (host memory) with the index's shape and modes. */
 mih_status mih_index_get_info(const mih_index *idx, mih_index_info *info);

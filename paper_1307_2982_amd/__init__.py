@@ -81,7 +81,9 @@ class Tuning(ctypes.Structure):
     _fields_ = [("probes_per_lane", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
                 ("blocks_per_cu", ctypes.c_uint32), ("occupancy_filter", ctypes.c_uint32),
                 ("sweep_shift", ctypes.c_uint32), ("sweep_bits", ctypes.c_uint32),
-                ("lookahead", ctypes.c_uint32)]
+                ("lookahead", ctypes.c_uint32), ("sweep_queries", ctypes.c_uint32),
+                ("buffer_mult", ctypes.c_uint32), ("small_batch", ctypes.c_uint32),
+                ("round_masks", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -113,7 +115,7 @@ EXPORTED = ["mih_build", "mih_knn", "mih_knn_ex", "linscan_knn", "linscan_knn_ex
             "mih_greedy_bit_order",
             "mih_status_str", "mih_index_get_info", "mih_index_table", "mih_get_tuning",
             "mih_set_tuning", "mih_autotune", "mih_server_create", "mih_server_submit", "mih_server_step",
-            "mih_server_poll", "mih_server_get_stats", "mih_server_destroy"]
+            "mih_server_poll", "mih_server_get_stats", "mih_server_destroy", "mih_random_read_rate"]
 
 _lib = None
 
@@ -193,6 +195,8 @@ def load():
     L.mih_server_get_stats.restype = i32
     L.mih_server_destroy.argtypes = [vp]
     L.mih_server_destroy.restype = None
+    L.mih_random_read_rate.argtypes = [vp, u64, u64, u32, vp, vp, ctypes.POINTER(ctypes.c_double)]
+    L.mih_random_read_rate.restype = i32
     _lib = L
     return L
 
@@ -277,21 +281,18 @@ class Index:
         _check(load().mih_get_tuning(self._h, ctypes.byref(t)), "mih_get_tuning")
         return t.as_dict()
 
-    def set_tuning(self, probes_per_lane: int | None = None, chunk: int | None = None,
-                   blocks_per_cu: int | None = None, occupancy_filter: int | None = None,
-                   sweep_shift: int | None = None, sweep_bits: int | None = None,
-                   lookahead: int | None = None):
-        """Launch tuning (speed only); fields left as None keep their value."""
+    def set_tuning(self, **fields):
+        """Launch tuning (speed only): any fields of mih_tuning (probes_per_lane,
+        chunk, blocks_per_cu, occupancy_filter, sweep_shift, sweep_bits,
+        lookahead, sweep_queries, buffer_mult, small_batch, round_masks); the
+        others keep their value."""
         cur = self.get_tuning()
-        probes_per_lane = cur["probes_per_lane"] if probes_per_lane is None else probes_per_lane
-        chunk = cur["chunk"] if chunk is None else chunk
-        blocks_per_cu = cur["blocks_per_cu"] if blocks_per_cu is None else blocks_per_cu
-        occupancy_filter = cur["occupancy_filter"] if occupancy_filter is None else occupancy_filter
-        sweep_shift = cur["sweep_shift"] if sweep_shift is None else sweep_shift
-        sweep_bits = cur["sweep_bits"] if sweep_bits is None else sweep_bits
-        lookahead = cur["lookahead"] if lookahead is None else lookahead
-        t = Tuning(probes_per_lane, chunk, blocks_per_cu, occupancy_filter, sweep_shift, sweep_bits,
-                   lookahead)
+        for f, v in fields.items():
+            if f not in cur:
+                raise TypeError(f"unknown tuning field {f!r}")
+            if v is not None:
+                cur[f] = int(v)
+        t = Tuning(**cur)
         _check(load().mih_set_tuning(self._h, ctypes.byref(t)), "mih_set_tuning")
 
     def autotune(self, queries: torch.Tensor, k) -> dict:
@@ -570,6 +571,23 @@ def linscan_knn_noalloc(codes: torch.Tensor, queries: torch.Tensor, k, out=None)
                                     dists.data_ptr(), _stream())
     _check(rc, "linscan_knn_noalloc")
     return _shape(ids, dists, total, nq, kk, kl)
+
+
+def random_read_rate(array: torch.Tensor, reads: int, depth: int = 8) -> dict:
+    """The device's rate of independent random 64-byte line reads from
+    ``array`` (a device tensor; a measurement helper, mih_random_read_rate)."""
+    if not array.is_cuda or not array.is_contiguous() or array.element_size() * array.numel() < 64:
+        raise ValueError("array must be a contiguous device tensor of at least 64 bytes")
+    sink = torch.zeros(1, dtype=torch.int64, device=array.device)
+    ms = ctypes.c_double()
+    words = array.numel() * array.element_size() // 8
+    _check(load().mih_random_read_rate(array.data_ptr(), words, reads, depth, sink.data_ptr(), _stream(),
+                                       ctypes.byref(ms)), "mih_random_read_rate")
+    threads = torch.cuda.get_device_properties(array.device).multi_processor_count * 8 * 256
+    per_lane = -(-reads // threads)
+    per_lane = -(-per_lane // depth) * depth
+    done = per_lane * threads
+    return {"reads": done, "ms": ms.value, "reads_per_s": done / (ms.value / 1e3), "depth": depth}
 
 
 # ------------------------------------------------------------------ serving

@@ -286,6 +286,8 @@ hipError_t mih_index::alloc(void **p, uint64_t bytes)
 mih_index::~mih_index()
 {
     batch_engine.reset();
+    if (small_dev) (void)hipFree(small_dev);
+    if (small_host) (void)hipHostFree(small_host);
     for (void *p : allocs) (void)hipFree(p);
 }
 
@@ -875,9 +877,14 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
         ((ix->table_mode == MIH_TABLE_DIRECT || ix->table_mode == MIH_TABLE_HEADS) && max_len >= 26) ? 1u : 0u;
     if (ix->table_mode == MIH_TABLE_HEADS && max_len >= 26) {
         // one entry read per occupied probe leaves registers for more
-        // probes in flight per lane (the autotuner's usual pick there)
-        ix->tuning.probes_per_lane = 8;
-        ix->tuning.chunk = 16384;
+        // probes in flight per lane; the large steps run in the partition
+        // kernel with a partition's occupancy bits in LDS (the autotuner's
+        // usual pick there)
+        ix->tuning.probes_per_lane = 4;
+        ix->tuning.chunk = 8192;
+        ix->tuning.sweep_shift = 3;
+        ix->tuning.sweep_bits = 17;
+        ix->tuning.sweep_queries = 4096;
     }
     ix->build_ms = ms_since(t0);
     *out = ix;
@@ -913,6 +920,131 @@ mih_status mih_knn_approx(const mih_index *cidx, const uint64_t *queries, uint32
 
 namespace {
 
+// Expected probes of an exact query with this k over uniform codes: the
+// shells of steps 0 .. r of the model radius r (Eq. 1 per step).  Used only
+// to pick the one-launch path for small batches.
+uint64_t model_probes(const mih_index *ix, uint32_t k)
+{
+    const uint32_t r = mih_model_radius(ix->n, ix->bits, k);
+    uint64_t probes = 0;
+    for (uint32_t t = 0; t <= r && t <= ix->t_all; ++t) {
+        const uint32_t rp = t / ix->m, s = ix->len[t % ix->m];
+        if (rp > s) continue;
+        uint64_t c = 1;
+        for (uint32_t i = 1; i <= rp; ++i) c = c * (s - rp + i) / i;
+        probes += c;
+    }
+    return probes;
+}
+
+// Most expected probes per query for the one-launch path: beyond this a
+// query's steps are better spread over many workgroups by the rounds.
+constexpr uint64_t kSmallProbes = 1ull << 18;
+
+// The batch in one launch (mih_small): the state of every query starts
+// from one upload of pinned staging (arguments, zeroed counters and
+// histograms); overflowed queries are returned in `ovf` for the engine's
+// exact re-run.
+mih_status small_batch(mih_index *ix, const uint64_t *queries, uint32_t nq, const std::vector<uint32_t> &kv,
+                       const std::vector<uint64_t> &row_off, uint32_t *out_ids, uint32_t *out_dists,
+                       hipStream_t s, bool timed, mih::EngineStats &es, std::vector<uint32_t> &ovf)
+{
+    const uint32_t nb = ix->bits + 1, nsteps = ix->t_all + 1;
+    std::vector<uint64_t> buf_off(nq);
+    std::vector<uint32_t> cap(nq);
+    uint64_t entries = 0;
+    for (uint32_t i = 0; i < nq; ++i) {
+        cap[i] = mih::search_capacity(kv[i], ix->tuning.buffer_mult);
+        buf_off[i] = entries;
+        entries += cap[i];
+    }
+    // the uploaded block: 64-bit arrays first, then the 32-bit ones
+    uint64_t up = 0;
+    auto field = [&](uint64_t bytes) { const uint64_t o = up; up += (bytes + 7) / 8 * 8; return o; };
+    const uint64_t o_bo = field(8ull * nq), o_ro = field(8ull * nq), o_st = field(32), o_k = field(4ull * nq),
+                   o_cap = field(4ull * nq), o_oc = field(8), o_tau = field(4ull * nq + 64),
+                   o_cnt = field(4ull * nq), o_hist = field(4ull * nq * nb), o_stop = field(4ull * nq),
+                   o_exit = field(4ull * nq), o_sc = field(4ull * nq * nsteps);
+    // then, not uploaded: the overflow list and the candidate buffers
+    const uint64_t o_ol = align_up(up, 256), o_buf = align_up(o_ol + 4ull * nq, 256);
+    const uint64_t dev_bytes = o_buf + 8 * std::max<uint64_t>(entries, 1);
+    if (dev_bytes > ix->small_dev_bytes) {
+        if (ix->small_dev) (void)hipFree(ix->small_dev);
+        ix->small_dev = nullptr;
+        ix->small_dev_bytes = 0;
+        MIH_TRY(hipMalloc(&ix->small_dev, dev_bytes));
+        ix->small_dev_bytes = dev_bytes;
+    }
+    const uint64_t host_bytes = up + 48;   // the upload, then the counters read back
+    if (host_bytes > ix->small_host_bytes) {
+        if (ix->small_host) (void)hipHostFree(ix->small_host);
+        ix->small_host = nullptr;
+        ix->small_host_bytes = 0;
+        MIH_TRY(hipHostMalloc(&ix->small_host, host_bytes, 0));
+        ix->small_host_bytes = host_bytes;
+    }
+    char *h = (char *)ix->small_host, *d = (char *)ix->small_dev;
+    std::memset(h, 0, up);
+    std::memcpy(h + o_bo, buf_off.data(), 8ull * nq);
+    std::memcpy(h + o_ro, row_off.data(), 8ull * nq);
+    std::memcpy(h + o_k, kv.data(), 4ull * nq);
+    std::memcpy(h + o_cap, cap.data(), 4ull * nq);
+    for (uint32_t i = 0; i < nq; ++i) {
+        reinterpret_cast<uint32_t *>(h + o_tau)[i] = ix->bits;
+        reinterpret_cast<uint32_t *>(h + o_stop)[i] = 0xFFFFFFFFu;
+    }
+    MIH_TRY(hipMemcpyAsync(d, h, up, hipMemcpyHostToDevice, s));
+
+    mih::MihArgs A = {};
+    mih::index_args(ix, A);
+    A.qb.queries = queries;
+    A.qb.k = (const uint32_t *)(d + o_k);
+    A.qb.tau = (uint32_t *)(d + o_tau);
+    A.qb.count = (uint32_t *)(d + o_cnt);
+    A.qb.cap = (const uint32_t *)(d + o_cap);
+    A.qb.buf_off = (const uint64_t *)(d + o_bo);
+    A.qb.buf = (uint64_t *)(d + o_buf);
+    A.qb.hist = (uint32_t *)(d + o_hist);
+    A.qb.nq = nq;
+    A.qb.bits = ix->bits;
+    A.stats = (unsigned long long *)(d + o_st);
+    mih::SmallArgs S = {};
+    S.nq = nq;
+    // as many workgroups per query as the device holds at once (up to 8)
+    const uint32_t resident =
+        num_cus() * (uint32_t)mih::mih_round_occupancy(A.W, A.tm, A.inline_codes, A.J, 3, 0);
+    S.groups = std::min<uint32_t>(8, std::max<uint32_t>(1, resident / nq));
+    S.row_off = (const uint64_t *)(d + o_ro);
+    S.out_ids = out_ids;
+    S.out_dists = out_dists;
+    S.stop = (uint32_t *)(d + o_stop);
+    S.exits = (uint32_t *)(d + o_exit);
+    S.step_cnt = (uint32_t *)(d + o_sc);
+    S.ovf_list = (uint32_t *)(d + o_ol);
+    S.ovf_count = (uint32_t *)(d + o_oc);
+    EventPair ev(timed);
+    ev.begin(s);
+    MIH_TRY(mih::mih_small(A, S, s));
+    ev.end(s);
+    // the statistics and the overflow count, read back together
+    char *hb = h + up;
+    MIH_TRY(hipMemcpyAsync(hb, d + o_st, 32, hipMemcpyDeviceToHost, s));
+    MIH_TRY(hipMemcpyAsync(hb + 32, d + o_oc, 4, hipMemcpyDeviceToHost, s));
+    MIH_TRY(hipStreamSynchronize(s));
+    const unsigned long long *hs = (const unsigned long long *)hb;
+    const uint32_t novf = *(const uint32_t *)(hb + 32);
+    es.probes += hs[0];
+    es.candidates += hs[1];
+    es.steps += hs[2];
+    es.appended += hs[3];
+    es.rounds += 1;
+    es.search_launches += 1;
+    if (timed) es.search_kernel_ms += ev.ms();
+    ovf.assign(novf, 0u);
+    if (novf) MIH_TRY(download(ovf.data(), S.ovf_list, 4ull * novf, s));
+    return MIH_OK;
+}
+
 mih_status knn_common(const mih_index *cidx, const uint64_t *queries, uint32_t nq, uint32_t k,
                       const uint32_t *k_per_query, uint32_t *out_ids, uint32_t *out_dists,
                       void *stream, mih_query_stats *stats, uint32_t max_t, uint32_t budget)
@@ -929,11 +1061,26 @@ mih_status knn_common(const mih_index *cidx, const uint64_t *queries, uint32_t n
     MIH_TRY_STATUS(read_k(nq, k, k_per_query, s, kv));
     std::vector<uint64_t> row_off;
     row_offsets(kv, row_off);
-    uint32_t slots = 0;
+    uint32_t slots = 0, kmax = 0;
     uint64_t pool = 0;
     for (uint32_t v : kv)
-        if (v) { slots++; pool += mih::search_capacity(v); }
+        if (v) { slots++; pool += mih::search_capacity(v, ix->tuning.buffer_mult); kmax = std::max(kmax, v); }
     if (slots == 0) return MIH_OK;
+    mih::EngineStats small_es;
+    std::vector<uint32_t> rest;   // queries left to the rounds (all, or the overflowed)
+    const bool small = max_t == 0xFFFFFFFFu && budget == 0 && nq <= ix->tuning.small_batch &&
+                       model_probes(ix, kmax) <= kSmallProbes;
+    if (small) {
+        MIH_TRY_STATUS(small_batch(ix, queries, nq, kv, row_off, out_ids, out_dists, s, stats != nullptr,
+                                   small_es, rest));
+        if (rest.empty()) {
+            if (stats) copy_stats(small_es, t0, stats);
+            return MIH_OK;
+        }
+        slots = (uint32_t)rest.size();
+        pool = 0;
+        for (uint32_t i : rest) pool += mih::search_capacity(kv[i], ix->tuning.buffer_mult);
+    }
     // one engine per index, kept while it is large enough
     if (!ix->batch_engine || ix->batch_engine->slots() < slots || ix->batch_engine->pool_entries() < pool) {
         ix->batch_engine.reset();
@@ -946,11 +1093,33 @@ mih_status knn_common(const mih_index *cidx, const uint64_t *queries, uint32_t n
     mih::Engine &eng = *ix->batch_engine;
     eng.set_stream(s);
     MIH_TRY(eng.reset_stats());
-    mih_status st = engine_batch(eng, queries, nq, kv, row_off, out_ids, out_dists, max_t, budget);
+    mih_status st = MIH_OK;
+    if (!small) {
+        st = engine_batch(eng, queries, nq, kv, row_off, out_ids, out_dists, max_t, budget);
+    } else {
+        // the overflowed queries of the one-launch path, one request each
+        const uint32_t W = ix->W;
+        std::vector<uint64_t> completed;
+        eng.set_count_unique(false);
+        eng.set_lookahead(true);
+        for (uint32_t i : rest) eng.submit(queries + (uint64_t)i * W, 1, &kv[i], &row_off[i], out_ids, out_dists);
+        while (st == MIH_OK && !eng.idle()) {
+            hipError_t e = eng.step(completed);
+            if (e != hipSuccess) { (void)hipGetLastError(); st = from_hip(e); }
+        }
+    }
     if (st != MIH_OK) { ix->batch_engine.reset(); return st; }
     if (stats) {
         mih::EngineStats es;
         MIH_TRY(eng.read_stats(es));
+        es.probes += small_es.probes;
+        es.candidates += small_es.candidates;
+        es.steps += small_es.steps;
+        es.appended += small_es.appended;
+        es.rounds += small_es.rounds;
+        es.reruns += (uint32_t)rest.size() * (small ? 1u : 0u);
+        es.search_kernel_ms += small_es.search_kernel_ms;
+        es.search_launches += small_es.search_launches;
         copy_stats(es, t0, stats);
     }
     return MIH_OK;
@@ -1115,6 +1284,11 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning)
     if (tuning->blocks_per_cu > 64 || tuning->occupancy_filter > 1) return MIH_ERR_INVALID;
     if (tuning->sweep_shift > 32 || tuning->sweep_bits < 10 || tuning->sweep_bits > 32) return MIH_ERR_INVALID;
     if (tuning->lookahead < 1 || tuning->lookahead > MIH_LOOKAHEAD_MAX) return MIH_ERR_INVALID;
+    if (tuning->sweep_queries < 64 || tuning->sweep_queries > 4096 || tuning->sweep_queries % 64 != 0)
+        return MIH_ERR_INVALID;
+    if (tuning->buffer_mult < 1 || tuning->buffer_mult > 64) return MIH_ERR_INVALID;
+    if (tuning->small_batch > 65536) return MIH_ERR_INVALID;
+    if (tuning->round_masks > (1u << 30)) return MIH_ERR_INVALID;
     std::lock_guard<std::mutex> lock(idx->mu);
     idx->tuning = *tuning;
     idx->tuning_version++;
@@ -1281,18 +1455,36 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
             }
     uint32_t max_len = 0;
     for (uint32_t j = 0; j < idx->m; ++j) max_len = std::max(max_len, idx->len[j]);
-    if (max_len >= mih::kSweepMinBits)
-        for (uint32_t J : {4u, 8u})
-            for (uint32_t bits : {18u, 20u}) {
-                mih_tuning t = idx->tuning;
-                t.probes_per_lane = J;
-                t.chunk = 64 * J * 32;
-                t.blocks_per_cu = 0;
-                t.occupancy_filter = filters - 1;
-                t.sweep_shift = 3;
-                t.sweep_bits = bits;
-                grid.push_back(t);
-            }
+    if (max_len >= mih::kSweepMinBits) {
+        if (filters == 2) {
+            // tables with an occupancy map sweep in the partition kernel
+            for (uint32_t J : {4u, 8u})
+                for (uint32_t bits : {17u, 18u}) {
+                    const uint32_t sq = 4096;
+                    mih_tuning t = idx->tuning;
+                    t.probes_per_lane = J;
+                    t.chunk = 64 * J * 32;
+                    t.blocks_per_cu = 0;
+                    t.occupancy_filter = 1;
+                    t.sweep_shift = 3;
+                    t.sweep_bits = bits;
+                    t.sweep_queries = sq;
+                    grid.push_back(t);
+                }
+        } else {
+            for (uint32_t J : {4u, 8u})
+                for (uint32_t bits : {18u, 20u}) {
+                    mih_tuning t = idx->tuning;
+                    t.probes_per_lane = J;
+                    t.chunk = 64 * J * 32;
+                    t.blocks_per_cu = 0;
+                    t.occupancy_filter = 0;
+                    t.sweep_shift = 3;
+                    t.sweep_bits = bits;
+                    grid.push_back(t);
+                }
+        }
+    }
     // one timing per setting, then two more of the three fastest (a single
     // call can be a few percent off); the best of a setting's timings counts
     std::vector<double> ms(grid.size(), 1e300);
@@ -1312,6 +1504,22 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
     }
     for (size_t i = 0; i < grid.size(); ++i)
         if (ms[i] < best_ms) { best_ms = ms[i]; best = grid[i]; }
+    // candidate-buffer capacity with the best launch: fewer entries admit
+    // more queries per round and touch less memory, more avoid the exact
+    // re-runs of overflowed queries (timed with them)
+    if (st == MIH_OK) {
+        const size_t base = grid.size();
+        for (uint32_t mult : {4u, 16u}) {
+            mih_tuning t = best;
+            t.buffer_mult = mult;
+            grid.push_back(t);
+        }
+        ms.resize(grid.size(), 1e300);
+        for (int rep = 0; rep < 2 && st == MIH_OK; ++rep)
+            for (size_t i = base; i < grid.size() && st == MIH_OK; ++i) time_one(i);
+        for (size_t i = base; i < grid.size(); ++i)
+            if (ms[i] < best_ms) { best_ms = ms[i]; best = grid[i]; }
+    }
     mih_status st2 = mih_set_tuning(idx, st == MIH_OK ? &best : &start);
     out.release();
     if (st != MIH_OK) return st;

@@ -30,8 +30,12 @@ private:
     uint64_t size_ = 0, free_total_ = 0;
 };
 
-// Candidate-buffer capacity given to a query with this k (entries).
-inline uint32_t search_capacity(uint32_t k) { return k == 0 ? 0u : (k * 8u > 2048u ? k * 8u : 2048u); }
+// Candidate-buffer capacity given to a query with this k (entries):
+// mult * max(k, 256).
+inline uint32_t search_capacity(uint32_t k, uint32_t mult)
+{
+    return k == 0 ? 0u : mult * (k > 256u ? k : 256u);
+}
 
 // The k of an r-neighbour query: no count ever reaches it, so its bound
 // stays at the radius.
@@ -41,6 +45,10 @@ constexpr uint32_t kRnnK = 0xFFFFFFFFu;
 constexpr uint32_t kRnnCapacity = 1024;
 
 class Engine;
+
+// The index-wide fields of the search kernels' arguments (tables, layout,
+// launch tuning), shared by the engine and the one-launch search.
+void index_args(const mih_index *ix, MihArgs &A);
 
 }  // namespace mih
 
@@ -59,10 +67,16 @@ struct mih_index {
     std::vector<void *> allocs;
     uint64_t device_bytes = 0;
     double build_ms = 0;
-    mih_tuning tuning = {4, 8192, 0, 0, 0, 18, MIH_LOOKAHEAD_DEFAULT};
+    mih_tuning tuning = {4, 8192, 0, 0, 0, 18, MIH_LOOKAHEAD_DEFAULT, 256, 8, 512, 0};
     uint32_t tuning_version = 0;
     std::mutex mu;
     std::unique_ptr<mih::Engine> batch_engine;   // reused by mih_knn calls
+    // the one-launch search of small batches: device state (grow-only) and
+    // pinned host staging for its arguments and counters
+    void *small_dev = nullptr;
+    uint64_t small_dev_bytes = 0;
+    void *small_host = nullptr;
+    uint64_t small_host_bytes = 0;
 
     hipError_t alloc(void **p, uint64_t bytes);
     ~mih_index();
@@ -119,7 +133,7 @@ public:
     hipError_t read_stats(EngineStats &out);
     hipError_t reset_stats();
     void set_stream(hipStream_t s) { s_ = s; }
-    bool can_ever_fit(uint32_t k) const { return search_capacity(k) <= pool_.size(); }
+    bool can_ever_fit(uint32_t k) const { return search_capacity(k, ix_->tuning.buffer_mult) <= pool_.size(); }
 
 private:
     struct Req {
@@ -162,7 +176,7 @@ private:
     uint32_t *new_slots_ = nullptr, *done_list_ = nullptr, *ovf_list_ = nullptr;
     uint32_t *bound_tau_ = nullptr, *bound_cap_ = nullptr;
     uint32_t *tmp_list_ = nullptr, *tmp_cnt_ = nullptr;
-    uint32_t *max_t_ = nullptr, *budget_ = nullptr, *uniq_ = nullptr;
+    uint32_t *max_t_ = nullptr, *budget_ = nullptr, *uniq_ = nullptr, *cursor_ = nullptr;
     bool count_unique_ = false, graph_count_unique_ = false;
     bool lookahead_ = true, graph_lookahead_ = true;
     uint64_t *out_ids_ = nullptr, *out_dists_ = nullptr;

@@ -123,7 +123,7 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
                    o_grp = take(sizeof(Group) * (ix_->t_all + 1)), o_ctrl = take(sizeof(Control)),
                    o_work = take(8 * (1 + kSweepXcds)), o_stats = take(8 * 4), o_adm = take(sizeof(AdmitRec) * S_),
                    o_tl = take(4ull * S_), o_tc = take(4ull * S_), o_mt = take(4ull * S_),
-                   o_bg = take(4ull * S_), o_uq = take(4ull * S_);
+                   o_bg = take(4ull * S_), o_uq = take(4ull * S_), o_cur = take(4ull * S_);
     hipError_t e = hipMalloc(&dev_, used);
     if (e != hipSuccess) { dev_ = nullptr; return e; }
     char *b = (char *)dev_;
@@ -157,6 +157,7 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
     max_t_ = (uint32_t *)(b + o_mt);
     budget_ = (uint32_t *)(b + o_bg);
     uniq_ = (uint32_t *)(b + o_uq);
+    cursor_ = (uint32_t *)(b + o_cur);
 
     const uint64_t pe = pool_entries ? pool_entries : 1;
     e = hipMalloc((void **)&pool_mem_, pe * 8);
@@ -180,32 +181,49 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
     return hipSuccess;
 }
 
-void Engine::fill_args(MihArgs &A) const
+void index_args(const mih_index *ix, MihArgs &A)
 {
-    A.tables = ix_->tables_dev;
-    A.codes = ix_->codes;
-    A.n = ix_->n;
-    A.W = ix_->W;
-    A.m = ix_->m;
-    A.bits = ix_->bits;
-    A.t_all = ix_->t_all;
-    A.tm = ix_->table_mode == MIH_TABLE_SORTED ? TM_SORTED
-         : ix_->table_mode == MIH_TABLE_GROUPED ? TM_GROUPED
-         : ix_->table_mode == MIH_TABLE_HEADS ? TM_HEADS : TM_DIRECT;
-    A.inline_codes = ix_->codes_mode == MIH_CODES_INLINE;
-    A.chunk = ix_->tuning.chunk;
-    A.J = ix_->tuning.probes_per_lane;
+    A.tables = ix->tables_dev;
+    A.codes = ix->codes;
+    A.n = ix->n;
+    A.W = ix->W;
+    A.m = ix->m;
+    A.bits = ix->bits;
+    A.t_all = ix->t_all;
+    A.tm = ix->table_mode == MIH_TABLE_SORTED ? TM_SORTED
+         : ix->table_mode == MIH_TABLE_GROUPED ? TM_GROUPED
+         : ix->table_mode == MIH_TABLE_HEADS ? TM_HEADS : TM_DIRECT;
+    A.inline_codes = ix->codes_mode == MIH_CODES_INLINE;
+    A.chunk = ix->tuning.chunk;
+    A.J = ix->tuning.probes_per_lane;
     // DIRECT and HEADS tables: test the occupancy map before the bucket
     // (HEADS entries also say whether a bucket is empty; the map is denser)
-    A.occ_filter = ix_->tuning.occupancy_filter &&
-                   (ix_->table_mode == MIH_TABLE_DIRECT || ix_->table_mode == MIH_TABLE_HEADS);
+    A.occ_filter = ix->tuning.occupancy_filter &&
+                   (ix->table_mode == MIH_TABLE_DIRECT || ix->table_mode == MIH_TABLE_HEADS);
+}
+
+void Engine::fill_args(MihArgs &A) const
+{
+    index_args(ix_, A);
+    // the work quantum in whole work items; steps cut into portions are
+    // never swept (a sweep runs a whole step)
+    A.quantum_items = ix_->tuning.round_masks
+                          ? std::max<uint32_t>(1u, (ix_->tuning.round_masks + A.chunk - 1) / A.chunk)
+                          : 0u;
+    A.cursor = cursor_;
     // distinct codes are counted in whole-step probing only
-    A.sweep_shift = count_unique_ ? 0u : ix_->tuning.sweep_shift;
+    A.sweep_shift = (count_unique_ || A.quantum_items) ? 0u : ix_->tuning.sweep_shift;
     A.count_unique = count_unique_ ? 1u : 0u;
     A.max_t = max_t_;
     A.budget = budget_;
     A.uniq = uniq_;
     A.sweep_bits = ix_->tuning.sweep_bits;
+    // tables with an occupancy map sweep in the partition kernel, with the
+    // partition's occupancy bits staged in LDS
+    A.sweep_part = A.occ_filter && (A.tm == TM_HEADS || A.tm == TM_DIRECT) &&
+                   mih_part_kernel_ok(A.W, A.tm, A.inline_codes, A.J);
+    A.part_bits = std::min(std::max(ix_->tuning.sweep_bits, kPartMinBits), kPartMaxBits);
+    A.sweep_q = A.sweep_part ? std::max<uint32_t>(ix_->tuning.sweep_queries, MIH_WAVE) : kSweepQueries;
     // lookahead fills the waves of the round kernel
     A.look_max = lookahead_ ? std::min<uint32_t>(std::max<uint32_t>(ix_->tuning.lookahead, 1u), kLookMax) : 1u;
     A.look_items = A.look_max > 1 ? round_grid_ * (MIH_BLOCK / MIH_WAVE) : 0u;
@@ -334,7 +352,7 @@ hipError_t Engine::admit()
                 continue;
             }
             uint64_t off;
-            const uint32_t cap = r.rnn ? kRnnCapacity : search_capacity(k);
+            const uint32_t cap = r.rnn ? kRnnCapacity : search_capacity(k, ix_->tuning.buffer_mult);
             if (free_slots_.empty() || !pool_.alloc(cap, off)) { stalled = true; break; }
             const uint32_t slot = free_slots_.back();
             free_slots_.pop_back();
@@ -373,10 +391,11 @@ hipError_t Engine::capture_graph()
     if (graph_) { (void)hipGraphDestroy(graph_); graph_ = nullptr; }
     MihArgs A;
     fill_args(A);
-    uint32_t per_cu = (uint32_t)mih_round_occupancy(A.W, A.tm, A.inline_codes, A.J, false);
+    uint32_t per_cu = (uint32_t)mih_round_occupancy(A.W, A.tm, A.inline_codes, A.J, 0, 0);
     if (ix_->tuning.blocks_per_cu && ix_->tuning.blocks_per_cu < per_cu) per_cu = ix_->tuning.blocks_per_cu;
     round_grid_ = cu_count() * per_cu;
-    uint32_t per_cu_sweep = (uint32_t)mih_round_occupancy(A.W, A.tm, A.inline_codes, A.J, true);
+    uint32_t per_cu_sweep =
+        (uint32_t)mih_round_occupancy(A.W, A.tm, A.inline_codes, A.J, A.sweep_part ? 2 : 1, A.part_bits);
     if (ix_->tuning.blocks_per_cu && ix_->tuning.blocks_per_cu < per_cu_sweep)
         per_cu_sweep = ix_->tuning.blocks_per_cu;
     sweep_grid_ = cu_count() * per_cu_sweep;

@@ -182,13 +182,14 @@ __device__ __forceinline__ uint32_t tighten_tau(const QueryBatch &qb, uint32_t q
 }
 
 // Ascending sort of P (a power of two, at most 4096) packed entries in LDS by
-// one workgroup (bitonic network); every thread of the block must call it.
+// one workgroup of any size (bitonic network); every thread of the block must
+// call it.
 __device__ __forceinline__ void block_bitonic_sort(uint64_t *v, uint32_t P)
 {
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
     for (uint32_t size = 2; size <= P; size <<= 1) {
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t i = tid; i < P / 2; i += MIH_BLOCK) {
+            for (uint32_t i = tid; i < P / 2; i += nt) {
                 const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
                 const uint32_t hi = lo + stride;
                 const bool up = (lo & size) == 0;

@@ -32,6 +32,9 @@ struct Group {
     uint32_t sweep_bits;  // swept: L, the key bits enumerated inside a partition; else 0
     uint32_t sweep_qc;    // swept: query chunks per partition
     uint64_t sweep_start; // first sweep item of the group (in each XCD's share)
+    uint32_t final;       // 1: the round finishes step t of its queries (the last
+                          // portion of a step cut by the work quantum, or all of it)
+    uint32_t pad;
 };
 
 // Queries per sweep work item (one per lane), the smallest table that is
@@ -41,6 +44,10 @@ constexpr uint32_t kSweepMinBits = 20;
 constexpr uint32_t kSweepXcds = 8;
 constexpr uint32_t kSweepBatch = 4;   // consecutive sweep items claimed at once
 static_assert(kSweepQueries <= MIH_WAVE, "one lane per query of a sweep item");
+// Partition kernel: the largest partition (key bits) whose occupancy bits
+// are staged in LDS (2^18 bits = 32 KiB).
+constexpr uint32_t kPartMaxBits = 18;
+constexpr uint32_t kPartMinBits = 10;
 
 // Device-resident control block of a search engine.
 struct Control {
@@ -78,8 +85,14 @@ struct MihArgs {
     uint32_t occ_filter;      // DIRECT: test the occupancy bitmap before the offsets
     uint32_t sweep_shift;     // sweep a group when its probes reach 2^s >> sweep_shift (0: never)
     uint32_t sweep_bits;      // key bits enumerated inside one sweep partition
+    uint32_t sweep_part;      // swept groups run in the partition kernel (occupancy tables)
+    uint32_t part_bits;       // partition kernel: key bits of a partition (<= kPartMaxBits)
+    uint32_t sweep_q;         // queries per sweep work item
     uint32_t look_items;      // a round may take further steps of its groups
                               // while its items stay within this (0: never)
+    uint32_t quantum_items;   // most work items of one query per round (0: a whole
+                              // step); a step with more continues in the next round
+    uint32_t *cursor;         // [slots] items of the current step already run
     uint32_t look_max;        // most steps of a group per round (<= kLookMax)
     uint64_t look_masks;      // ... and while its shell masks stay within this
     QueryBatch qb;            // per-slot state (qb.queries is slot storage)
@@ -106,7 +119,27 @@ struct MihArgs {
 hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s);
 // The swept groups of the round (returns at once when there are none).
 hipError_t mih_sweep(const MihArgs &A, uint32_t grid, hipStream_t s);
-int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, bool sweep);
+// Workgroups per CU of a kernel (which: 0 round, 1 sweep, 2 partition).
+int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, int which,
+                        uint32_t part_bits);
+// One launch for a small batch of exact queries: `groups` workgroups per
+// query run every step and the last to leave writes the top-k rows.
+struct SmallArgs {
+    uint32_t nq;
+    uint32_t groups;          // workgroups per query
+    const uint64_t *row_off;  // [nq] output row of each query
+    uint32_t *out_ids, *out_dists;
+    uint32_t *stop;           // [nq] ~0, then the step after which the query stopped
+    uint32_t *exits;          // [nq] 0: workgroups that have left
+    uint32_t *step_cnt;       // [nq][t_all + 1] 0: workgroups done with each step
+    uint32_t *ovf_list;       // queries whose buffer overflowed (no rows written)
+    uint32_t *ovf_count;      // 0 on entry
+};
+// A.qb describes the batch (queries [nq][W], k, cap, buf_off; tau = bits,
+// count = 0 and hist = 0 on entry); A.stats (4 counters) zero on entry.
+hipError_t mih_small(const MihArgs &A, const SmallArgs &S, hipStream_t s);
+// Whether the partition kernel exists for this layout.
+bool mih_part_kernel_ok(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J);
 bool mih_probes_per_lane_ok(uint32_t J);
 // Start of a round: merge survivors and new queries into the active list.
 hipError_t mih_regroup(const MihArgs &A, hipStream_t s);

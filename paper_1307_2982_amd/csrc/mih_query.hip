@@ -29,6 +29,7 @@
 // to their next non-empty step and regroups the active queries by step.
 #include "mih_common.h"
 #include "mih_query.h"
+#include "topk_dev.h"
 
 namespace {
 
@@ -166,6 +167,88 @@ __device__ __forceinline__ uint32_t query_key(const mih::MihArgs &A, uint32_t q,
     return table_key<W>(g, A.tables[a]);
 }
 
+// The buckets of a lane's J consecutive masks of rank r0 .. r0 + nmy - 1
+// (among the `nbits`-bit masks with `rho` set bits, xored into key_base):
+// their table positions [lo, lo + cnt) and, for HEADS tables, their first
+// codes.  Empty buckets (and masks past nmy) get cnt = 0.
+template <int W, int TM, int J>
+__device__ __forceinline__ void lookup_block(const mih::MihArgs &A, const TableDev &T, uint32_t key_base,
+                                             uint32_t nbits, uint32_t rho, uint32_t r0, uint32_t nmy,
+                                             const uint32_t (*binom)[MIH_BINOM_N], uint32_t (&lo)[J],
+                                             uint32_t (&cnt)[J], uint64_t (&head_code)[J])
+{
+    uint32_t keys[J];
+    uint32_t mask = nmy ? unrank_mask(r0, rho, nbits, binom) : 0u;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        keys[j] = key_base ^ mask;
+        if ((uint32_t)j + 1 < nmy && rho > 0) mask = next_mask(mask);
+    }
+    // DIRECT tables with the occupancy filter: one bit per bucket says
+    // whether it holds codes; only occupied buckets read their offsets.
+    // GROUPED tables: the group record holds the same bits.
+    uint32_t occ_bits = ~0u;
+    uint32_t gbase[J];
+    if (TM == mih::TM_GROUPED) {
+        occ_bits = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            gbase[j] = 0;
+            if ((uint32_t)j < nmy) {
+                const uint64_t rec = T.grp[keys[j] >> 5];
+                const uint32_t bit = keys[j] & 31, occ = (uint32_t)rec;
+                if ((occ >> bit) & 1u) occ_bits |= 1u << j;
+                // every occupied bucket below this one in the group holds
+                // at least one code: the bucket starts no earlier than here
+                gbase[j] = (uint32_t)(rec >> 32) + __popc(occ & ((1u << bit) - 1u));
+            }
+        }
+    } else if ((TM == mih::TM_HEADS || TM == mih::TM_DIRECT) && A.occ_filter) {
+        occ_bits = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if ((uint32_t)j < nmy && ((T.occ[keys[j] >> 5] >> (keys[j] & 31)) & 1u)) occ_bits |= 1u << j;
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        cnt[j] = 0;
+        lo[j] = 0;
+        if ((uint32_t)j < nmy && ((occ_bits >> j) & 1u)) {
+            const uint32_t key = keys[j];
+            if (TM == mih::TM_GROUPED) {
+                group_scan<W>(T, A.n, key, gbase[j], lo[j], cnt[j]);
+            } else if (TM == mih::TM_HEADS) {
+                const BucketHead h = T.head[key];   // one 16-byte entry, one line
+                lo[j] = h.start;
+                cnt[j] = h.count;
+                head_code[j] = h.code;
+            } else if (TM == mih::TM_DIRECT) {
+                const uint32_t b0 = T.off[key];
+                const uint32_t b1 = T.off[(uint64_t)key + 1];
+                lo[j] = b0;
+                cnt[j] = b1 - b0;
+            } else {
+                const uint32_t cell = key >> (T.len - T.dir_bits);
+                uint32_t x0 = T.dir[cell], x1 = T.dir[(uint64_t)cell + 1];
+                // first position with keys >= key, then first with keys > key
+                uint32_t l = x0, h = x1;
+                while (l < h) {
+                    uint32_t mid = l + ((h - l) >> 1);
+                    if (T.keys[mid] < key) l = mid + 1; else h = mid;
+                }
+                uint32_t e = l;
+                h = x1;
+                while (e < h) {
+                    uint32_t mid = e + ((h - e) >> 1);
+                    if (T.keys[mid] <= key) e = mid + 1; else h = mid;
+                }
+                lo[j] = l;
+                cnt[j] = e - l;
+            }
+        }
+    }
+}
+
 // Part of step t of query q: the buckets key_base ^ mask for the masks of
 // rank [rb, re) among the `nbits`-bit masks with `rho` set bits.  A whole
 // step is key_base = the query's key, nbits = s_a, rho = t / m; one key
@@ -191,77 +274,9 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
     for (uint32_t base = rb; base < re; base += MIH_WAVE * J) {
         const uint32_t r0 = base + lane * J;
         const uint32_t nmy = r0 < re ? (re - r0 < (uint32_t)J ? re - r0 : (uint32_t)J) : 0u;
-        uint32_t lo[J], cnt[J], keys[J];
+        uint32_t lo[J], cnt[J];
         uint64_t head_code[J];   // HEADS: the first code of each bucket
-        uint32_t mask = nmy ? unrank_mask(r0, rho, nbits, binom) : 0u;
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            keys[j] = key_base ^ mask;
-            if ((uint32_t)j + 1 < nmy && rho > 0) mask = next_mask(mask);
-        }
-        // DIRECT tables with the occupancy filter: one bit per bucket says
-        // whether it holds codes; only occupied buckets read their offsets.
-        // GROUPED tables: the group record holds the same bits.
-        uint32_t occ_bits = ~0u;
-        uint32_t gbase[J];
-        if (TM == mih::TM_GROUPED) {
-            occ_bits = 0;
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                gbase[j] = 0;
-                if ((uint32_t)j < nmy) {
-                    const uint64_t rec = T.grp[keys[j] >> 5];
-                    const uint32_t bit = keys[j] & 31, occ = (uint32_t)rec;
-                    if ((occ >> bit) & 1u) occ_bits |= 1u << j;
-                    // every occupied bucket below this one in the group holds
-                    // at least one code: the bucket starts no earlier than here
-                    gbase[j] = (uint32_t)(rec >> 32) + __popc(occ & ((1u << bit) - 1u));
-                }
-            }
-        } else if ((TM == mih::TM_HEADS || TM == mih::TM_DIRECT) && A.occ_filter) {
-            occ_bits = 0;
-#pragma unroll
-            for (int j = 0; j < J; ++j)
-                if ((uint32_t)j < nmy && ((T.occ[keys[j] >> 5] >> (keys[j] & 31)) & 1u)) occ_bits |= 1u << j;
-        }
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            cnt[j] = 0;
-            lo[j] = 0;
-            if ((uint32_t)j < nmy && ((occ_bits >> j) & 1u)) {
-                const uint32_t key = keys[j];
-                if (TM == mih::TM_GROUPED) {
-                    group_scan<W>(T, A.n, key, gbase[j], lo[j], cnt[j]);
-                } else if (TM == mih::TM_HEADS) {
-                    const BucketHead h = T.head[key];   // one 16-byte entry, one line
-                    lo[j] = h.start;
-                    cnt[j] = h.count;
-                    head_code[j] = h.code;
-                } else if (TM == mih::TM_DIRECT) {
-                    const uint32_t b0 = T.off[key];
-                    const uint32_t b1 = T.off[(uint64_t)key + 1];
-                    lo[j] = b0;
-                    cnt[j] = b1 - b0;
-                } else {
-                    const uint32_t cell = key >> (T.len - T.dir_bits);
-                    uint32_t x0 = T.dir[cell], x1 = T.dir[(uint64_t)cell + 1];
-                    // first position with keys >= key, then first with keys > key
-                    uint32_t l = x0, h = x1;
-                    while (l < h) {
-                        uint32_t mid = l + ((h - l) >> 1);
-                        if (T.keys[mid] < key) l = mid + 1; else h = mid;
-                    }
-                    uint32_t e = l;
-                    h = x1;
-                    while (e < h) {
-                        uint32_t mid = e + ((h - e) >> 1);
-                        if (T.keys[mid] <= key) e = mid + 1; else h = mid;
-                    }
-                    lo[j] = l;
-                    cnt[j] = e - l;
-                }
-            }
-        }
+        lookup_block<W, TM, J>(A, T, key_base, nbits, rho, r0, nmy, binom, lo, cnt, head_code);
         // stage the non-empty buckets of the wave with the running count of
         // candidates before each, then walk the candidates 64 at a time
         uint32_t ne = 0, tc = 0;
@@ -406,14 +421,17 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
         uint32_t t = G->t + u;
         const uint32_t rp = t / A.m;
         const uint32_t M = binom[A.tables[t - rp * A.m].len][rp];
+        // the window's first step resumes where the last round's portion ended
+        if (u == 0 && A.quantum_items) part += A.cursor[q];
         const uint32_t rb = part * chunk;
         const uint32_t re = rb + chunk < M ? rb + chunk : M;
         uint64_t gq[W];
         const uint32_t a0 = t - rp * A.m;
         process_step<W, TM, INLINE, J>(A, q, t, query_key<W>(A, q, a0, gq), A.tables[a0].len, rp, rb, re,
                                        binom, stage_pos[wave], stage_cum[wave], stage_code[wave], ws);
-        if (ipq != 1 || steps != 1) continue;
-        // the whole step belonged to this wave: keep going while steps are small
+        if (ipq != 1 || steps != 1 || !G->final) continue;
+        // the whole step (or its last portion) belonged to this wave: keep
+        // going while steps are small
         for (;;) {
             const uint32_t tau = tighten_tau(A.qb, q, __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q)));
             if (tau <= t || t >= A.t_all || t >= A.max_t[q]) break;
@@ -430,7 +448,10 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
                                                stage_code[wave], ws);
             }
             t = tn;
-            if (lane == 0) A.t[q] = t;
+            if (lane == 0) {
+                A.t[q] = t;
+                A.cursor[q] = 0;
+            }
         }
     }
     if (lane == 0) {
@@ -556,7 +577,7 @@ __device__ void sweep_item(const mih::MihArgs &A, const mih::Group &G, uint32_t 
         uint64_t g[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) g[w] = A.qb.queries[(uint64_t)q * W + w];
-        const uint32_t key = table_key<W>(g, T);
+        const uint32_t key = table_key<W>(g, A.tables[a]);   // not the local copy (see part_queries)
         const uint32_t wgt = __popc((L >= 32 ? 0u : key >> L) ^ h);
         const uint32_t rho = wgt <= rp ? rp - wgt : 0xFFFFFFFFu;
         M = rho <= L ? binom[L][rho] : 0u;
@@ -747,6 +768,516 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_sweep_kernel(mih::MihArgs A)
     }
 }
 
+// ------------------------------------------------------------------------
+// Partition sweep of large steps on tables with an occupancy map (DIRECT
+// with the occupancy filter, HEADS).
+//
+// A step of r' over a table of s bits probes C(s, r') buckets per query;
+// for the large steps of a big batch that is more probes than the table has
+// buckets, and probing query by query reads the same occupancy words over
+// and over from HBM (one 64-byte line holds the bits of 512 buckets).  Here
+// the key space is cut into partitions of 2^L values; a work item is one
+// partition and a chunk of the group's queries, run by one workgroup: the
+// partition's occupancy bits (2^L / 8 bytes) are staged in LDS once, then
+// every query of the chunk enumerates the buckets of its step that fall in
+// the partition (those whose high s - L bits differ from the query's in w
+// places, with r' - w of the low L bits flipped; over all partitions these
+// are exactly the C(s, r') buckets of the step, by Vandermonde's identity)
+// and tests them against LDS.  Only occupied buckets are read from HBM.
+// Partitions are dealt to the eight XCDs in turn (workgroups are dispatched
+// to them in turn) and the chunks of one partition are consecutive items,
+// so that the workgroups of an XCD work on few partitions at a time and
+// share their bucket lines in that XCD's L2.
+//
+// A lane walks J consecutive masks of the flat list of the wave's 64
+// queries and tests them against LDS; the occupied buckets go to a queue
+// in LDS, and once it holds a full pass, every lane reads kPartDepth bucket
+// entries at once (HEADS: offset, size and first code in one 16-byte read),
+// so that the wave keeps 64 kPartDepth independent reads in flight.  Most
+// buckets hold one code; the further codes of a bucket are read level by
+// level, kPartDepth at a time.
+constexpr uint32_t kPartDepth = 4;
+
+template <int W, int J>
+struct PartLds {
+    // the queue holds what a pass leaves plus one block of masks
+    static constexpr uint32_t kQueue = MIH_WAVE * (kPartDepth + J);
+    uint32_t qstart[MIH_WAVE + 1];   // exclusive prefix of the masks per query
+    uint32_t qkey[MIH_WAVE];         // partition bits | low bits of the query's key
+    uint32_t qrho[MIH_WAVE];         // set bits of the query's masks in the partition
+    uint32_t qslot[MIH_WAVE];
+    uint32_t qtau[MIH_WAVE];         // bound of the query (refreshed after appends)
+    uint64_t qg[MIH_WAVE][W];        // the query's words
+    uint32_t queue[kQueue];          // occupied buckets: low key bits << 6 | wave query
+};
+
+// Verify candidate `code` (table position pos) of query k of the wave:
+// full distance, the first-encounter rule, then append.  Returns whether
+// it was kept.
+template <int W, bool TINL, class S>
+__device__ __forceinline__ bool part_verify(const mih::MihArgs &A, const TableDev &T, uint32_t a, uint32_t rp,
+                                            const S &P, uint32_t k, const uint64_t (&code)[W], uint32_t pos,
+                                            uint32_t id)
+{
+    uint64_t g[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) g[w] = P.qg[k][w];
+    const uint32_t d = hamming<W>(code, g);
+    if (d > P.qtau[k]) return false;
+    uint64_t x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = code[w] ^ g[w];
+    for (uint32_t j = 0; j < A.m; ++j) {
+        if (j == a) continue;
+        const uint32_t dj = table_dist<W>(x, A.tables[j]);
+        if (j < a ? dj <= rp : dj < rp) return false;
+    }
+    if (TINL) id = T.ids[pos];
+    const uint32_t q = P.qslot[k];
+    const uint32_t slot = atomicAdd(&A.qb.count[q], 1u);
+    if (slot < A.qb.cap[q]) A.qb.buf[A.qb.buf_off[q] + slot] = ((uint64_t)d << 32) | id;
+    atomicAdd(&A.qb.hist[(uint64_t)q * (A.qb.bits + 1) + d], 1u);
+    return true;
+}
+
+// One pass over queue entries [head, head + cnt), cnt <= 64 kPartDepth: the
+// buckets' entries, then their candidates.  Returns the wave queries that
+// received candidates.
+template <int W, int TM, bool INLINE, int J>
+__device__ uint64_t part_drain(const mih::MihArgs &A, const TableDev &T, uint32_t a, uint32_t rp, uint32_t h,
+                               uint32_t L, PartLds<W, J> &S, uint32_t head, uint32_t cnt, WaveStats &ws)
+{
+    constexpr uint32_t D = kPartDepth, Q = PartLds<W, J>::kQueue;
+    const uint32_t lane = lane_id();
+    const bool tinl = INLINE || T.codes != nullptr;
+    uint32_t lo[D], num[D], qi[D];
+    uint64_t first[D];
+#pragma unroll
+    for (uint32_t d = 0; d < D; ++d) {
+        const uint32_t e = lane + MIH_WAVE * d;
+        lo[d] = num[d] = qi[d] = 0;
+        first[d] = 0;
+        if (e < cnt) {
+            const uint32_t v = S.queue[(head + e) % Q];
+            const uint32_t key = (h << L) | (v >> 6);
+            qi[d] = v & 63u;
+            if (TM == mih::TM_HEADS) {
+                const BucketHead hd = T.head[key];
+                lo[d] = hd.start;
+                num[d] = hd.count;
+                first[d] = hd.code;
+            } else {
+                const uint32_t b0 = T.off[key];
+                lo[d] = b0;
+                num[d] = T.off[(uint64_t)key + 1] - b0;
+            }
+        }
+    }
+    uint32_t tc = 0, most = 0;
+#pragma unroll
+    for (uint32_t d = 0; d < D; ++d) {
+        tc += num[d];
+        most = num[d] > most ? num[d] : most;
+    }
+    ws.candidates += wave_sum(tc);
+    uint64_t touched = 0;
+    // level c: the c-th code of each of the lane's buckets (HEADS: level 0
+    // came with the entries)
+    for (uint32_t c = 0; __ballot(c < most); ++c) {
+        uint64_t code[D][W];
+        uint32_t id[D];
+#pragma unroll
+        for (uint32_t d = 0; d < D; ++d) {
+            id[d] = 0;
+            if (c < num[d]) {
+                const uint32_t pos = lo[d] + c;
+                if (TM == mih::TM_HEADS && c == 0) {
+                    code[d][0] = first[d];
+                } else if (tinl) {
+                    load_code<W>(T.codes + (uint64_t)pos * W, code[d]);
+                } else {
+                    id[d] = T.ids[pos];
+                    load_code<W>(A.codes + (uint64_t)id[d] * W, code[d]);
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t d = 0; d < D; ++d) {
+            if (c < num[d] && (tinl ? part_verify<W, true>(A, T, a, rp, S, qi[d], code[d], lo[d] + c, id[d])
+                                    : part_verify<W, false>(A, T, a, rp, S, qi[d], code[d], lo[d] + c, id[d])))
+                touched |= 1ull << qi[d];
+        }
+    }
+    return touched;
+}
+
+// Tighten the bound of every wave query in `touched` (any lane's bits).
+template <int W, int J>
+__device__ void part_tighten(const mih::MihArgs &A, PartLds<W, J> &S, uint64_t touched)
+{
+    uint64_t tq = touched;
+#pragma unroll
+    for (int sh = 1; sh < MIH_WAVE; sh <<= 1) tq |= (uint64_t)__shfl_xor((long long)tq, sh, MIH_WAVE);
+    tq = u64_uniform<1>(tq);
+    while (tq) {
+        const uint32_t k = (uint32_t)__ffsll((long long)tq) - 1;
+        tq &= tq - 1;
+        const uint32_t nt = tighten_tau(A.qb, S.qslot[k], S.qtau[k]);
+        if (lane_id() == 0) S.qtau[k] = nt;
+    }
+    wave_lds_sync();
+}
+
+// The queries i0 .. i0 + nq - 1 (at most 64) of the group at step t whose
+// active entries start at slot_start, against partition h of L key bits,
+// whose occupancy bits are in `occ` (bit v of the partition: word v / 32).
+template <int W, int TM, bool INLINE, int J>
+__device__ void part_queries(const mih::MihArgs &A, uint32_t t, uint32_t slot_start, uint32_t L, uint32_t h,
+                             uint32_t i0, uint32_t nq, const uint32_t *occ,
+                             const uint32_t (*binom)[MIH_BINOM_N], PartLds<W, J> &S, WaveStats &ws)
+{
+    constexpr uint32_t D = kPartDepth, Q = PartLds<W, J>::kQueue;
+    static_assert(Q >= MIH_WAVE * (kPartDepth + J), "queue holds a pass's rest and a block");
+    const uint32_t lane = lane_id();
+    const uint32_t rp = t / A.m, a = t - rp * A.m;
+    const TableDev &T = A.tables[a];
+    const uint32_t low = (1u << L) - 1u;
+
+    uint32_t M = 0;
+    if (lane < nq) {
+        const uint32_t q = A.active[slot_start + i0 + lane];
+        uint64_t g[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) g[w] = A.qb.queries[(uint64_t)q * W + w];
+        const uint32_t key = table_key<W>(g, T);
+        const uint32_t wgt = __popc((key >> L) ^ h);
+        const uint32_t rho = wgt <= rp ? rp - wgt : 0xFFFFFFFFu;
+        M = rho <= L ? binom[L][rho] : 0u;
+        S.qkey[lane] = (h << L) | (key & low);
+        S.qrho[lane] = rho <= L ? rho : 0u;
+        S.qslot[lane] = q;
+        S.qtau[lane] = load_relaxed(A.qb.tau + q);
+#pragma unroll
+        for (int w = 0; w < W; ++w) S.qg[lane][w] = g[w];
+    }
+    const uint32_t incl = wave_inclusive_sum(M);
+    S.qstart[lane] = incl - M;
+    if (lane == MIH_WAVE - 1) S.qstart[MIH_WAVE] = incl;
+    wave_lds_sync();
+    const uint32_t total = S.qstart[MIH_WAVE];
+    ws.probes += total;
+
+    // each lane walks one contiguous range of the flat list, so that it
+    // unranks a mask once per sub-chunk and steps with Gosper's rule after
+    // (32-bit: partitions have at most 18 key bits)
+    const uint32_t per_lane = (total + MIH_WAVE - 1) / MIH_WAVE;
+    const uint32_t f0 = lane * per_lane;
+    const uint32_t f_end = f0 + per_lane < total ? f0 + per_lane : total;
+    uint32_t cur = 0, mask = 0, qkey = 0, next_start = 0;
+    if (f0 < f_end) {
+        // the query whose masks hold flat index f0: the last start <= f0
+        uint32_t l = 0, hh = MIH_WAVE;
+        while (hh - l > 1) {
+            const uint32_t mid = (l + hh) >> 1;
+            if (S.qstart[mid] <= f0) l = mid; else hh = mid;
+        }
+        cur = l;
+        mask = unrank_mask(f0 - S.qstart[cur], S.qrho[cur], L, binom);
+        qkey = S.qkey[cur];
+        next_start = S.qstart[cur + 1];
+    }
+    uint32_t head = 0, tail = 0;   // queue positions (slot = position mod Q)
+    for (uint32_t b = 0; b < per_lane; b += J) {
+        // the J keys of the block (registers; a query boundary reads the
+        // next query's entries), then their J occupancy words together,
+        // then the occupied ones to the queue
+        uint32_t v[J], qc[J];
+        bool valid[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t f = f0 + b + j;
+            valid[j] = f < f_end;
+            v[j] = (qkey ^ mask) & low;
+            qc[j] = cur;
+            if (f + 1 < next_start) {
+                // Gosper's next mask with the same number of set bits
+                const uint32_t c = mask & (0u - mask);
+                const uint32_t r = mask + c;
+                mask = (((r ^ mask) >> 2) >> __builtin_ctz(c | (c == 0 ? 1u : 0u))) | r;
+            } else if (f + 1 < f_end) {
+                do { ++cur; } while (S.qstart[cur + 1] <= f + 1);   // f + 1 < total: this stops
+                mask = (1u << S.qrho[cur]) - 1u;                   // the first mask of that query
+                qkey = S.qkey[cur];
+                next_start = S.qstart[cur + 1];
+            }
+        }
+        uint32_t word[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) word[j] = valid[j] ? occ[v[j] >> 5] : 0u;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const bool hit = (word[j] >> (v[j] & 31)) & 1u;
+            const uint64_t bal = __ballot(hit);
+            if (hit) S.queue[(tail + lanes_below(bal)) % Q] = (v[j] << 6) | qc[j];
+            tail += (uint32_t)__popcll(bal);
+        }
+        if (tail - head >= MIH_WAVE * D) {
+            wave_lds_sync();
+            uint64_t touched = 0;
+            for (; tail - head >= MIH_WAVE * D; head += MIH_WAVE * D)
+                touched |= part_drain<W, TM, INLINE, J>(A, T, a, rp, h, L, S, head, MIH_WAVE * D, ws);
+            part_tighten<W, J>(A, S, touched);   // ends with a wave sync: the slots read may be reused
+        }
+    }
+    if (tail != head) {
+        wave_lds_sync();
+        const uint64_t touched = part_drain<W, TM, INLINE, J>(A, T, a, rp, h, L, S, head, tail - head, ws);
+        part_tighten<W, J>(A, S, touched);
+    }
+}
+
+template <int W, int TM, bool INLINE, int J>
+__global__ __launch_bounds__(MIH_BLOCK) void mih_part_kernel(mih::MihArgs A)
+{
+    __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
+    __shared__ PartLds<W, J> pq[kWaves];
+    extern __shared__ uint32_t occ[];   // (1 << part_bits) / 32 words
+    __shared__ unsigned long long s_item;
+    const uint64_t per_xcd = A.ctrl->sweep_items;
+    if (per_xcd == 0) return;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += MIH_BLOCK)
+        binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
+
+    const uint32_t n_groups = A.ctrl->n_groups;
+    const uint32_t home = blockIdx.x % mih::kSweepXcds;
+    uint32_t staged_h = 0xFFFFFFFFu, staged_g = 0xFFFFFFFFu;   // partition whose bits are in occ
+    WaveStats ws = {0, 0};
+    for (uint32_t k = 0; k < mih::kSweepXcds; ++k) {
+        const uint32_t x = (home + k) % mih::kSweepXcds;
+        for (;;) {
+            __syncthreads();   // the previous item is done with occ and s_item
+            if (tid == 0) s_item = atomicAdd(A.work_sweep + x, 1ull);
+            __syncthreads();
+            const uint64_t item = s_item;
+            if (item >= per_xcd) break;
+            uint32_t gl = 0, gh = n_groups;
+            while (gh - gl > 1) {
+                const uint32_t mid = (gl + gh) >> 1;
+                if (A.groups[mid].sweep_start <= item) gl = mid; else gh = mid;
+            }
+            // the fields of the group that the item needs (kept in registers)
+            const mih::Group *Gp = A.groups + gl;
+            const uint32_t qc = Gp->sweep_qc, gt = Gp->t, gcount = Gp->count, gslot = Gp->slot_start;
+            const uint32_t L = Gp->sweep_bits;
+            if (qc == 0) continue;   // not a swept group (cannot own an item)
+            const uint64_t rel = item - Gp->sweep_start;
+            const uint32_t h = (uint32_t)(rel / qc) * mih::kSweepXcds + x;
+            const uint32_t c = (uint32_t)(rel % qc);
+            if (h != staged_h || gl != staged_g) {
+                const uint32_t a = gt % A.m;
+                const uint32_t nw = (1u << L) >> 5;
+                const uint32_t *src = A.tables[a].occ + ((uint64_t)h << (L - 5));
+                for (uint32_t i = tid; i < nw; i += MIH_BLOCK) occ[i] = src[i];
+                staged_h = h;
+                staged_g = gl;
+                __syncthreads();
+            }
+            const uint32_t q0 = c * A.sweep_q;
+            const uint32_t qn = gcount - q0 < A.sweep_q ? gcount - q0 : A.sweep_q;
+            for (uint32_t s0 = wave * MIH_WAVE; s0 < qn; s0 += kWaves * MIH_WAVE) {
+                const uint32_t nq = qn - s0 < MIH_WAVE ? qn - s0 : MIH_WAVE;
+                part_queries<W, TM, INLINE, J>(A, gt, gslot, L, h, q0 + s0, nq, occ, binom, pq[wave], ws);
+            }
+        }
+    }
+    if (lane == 0) {
+        atomicAdd(&A.stats[0], (unsigned long long)ws.probes);
+        atomicAdd(&A.stats[1], (unsigned long long)ws.candidates);
+    }
+}
+
+// ------------------------------------------------------------------------
+// One launch for a small batch: every query is taken by G workgroups, which
+// run all its steps (Algorithm 3) on the device with no host round trip and
+// no regroup between steps.  Steps go in windows: a window is one step, or
+// consecutive steps whose masks together fill at most one pass of the
+// query's waves.  Each workgroup takes its share of every window
+// (contiguous ranges of masks, one per wave), in step order; the workgroup
+// that finishes a window last (a counter per query and step) knows that
+// steps 0 .. tw are complete, tests termination (Proposition 2) and, if the
+// query is done, raises its stop flag.  The others do not wait for that test:
+// they go on with the next window and leave at the next window boundary
+// once the flag is up.  Steps they run ahead of the decision only add codes
+// farther than the stop step, which is the engine's lookahead and changes
+// no result.  A workgroup runs at most one window ahead of the completed
+// ones (a bounded wait at each window; past the bound it goes on).  The
+// workgroup that leaves last writes the top-k rows (or lists the query for
+// an exact re-run when its candidate buffer overflowed).  This is for batches too
+// small to fill the device with rounds, where the latency of the rounds,
+// not the number of probes, sets the time.
+template <int J>
+constexpr uint32_t small_waves() { return J >= 16 ? 4 : (J >= 8 ? 8 : 16); }   // LDS staging per wave
+// Most polls of a workgroup waiting for a step of its query to complete
+// (each a device-scope load and a short sleep: a few milliseconds at most).
+constexpr uint32_t kSmallPolls = 4096;
+
+template <int W, int TM, bool INLINE, int J>
+__global__ __launch_bounds__(small_waves<J>() * MIH_WAVE) void mih_small_kernel(
+    mih::MihArgs A, mih::SmallArgs S)
+{
+    constexpr uint32_t kW = small_waves<J>(), kThreads = kW * MIH_WAVE;
+    __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
+    // the staging of the search and the top-k of the last workgroup share LDS
+    struct Stage {
+        uint32_t pos[kW][MIH_WAVE * J];
+        uint32_t cum[kW][MIH_WAVE * J];
+        uint64_t code[kW][TM == mih::TM_HEADS ? MIH_WAVE * J : 1];
+    };
+    __shared__ union {
+        Stage st;
+        FinalizeLds fin;
+    } U;
+    uint32_t (&stage_pos)[kW][MIH_WAVE * J] = U.st.pos;
+    uint32_t (&stage_cum)[kW][MIH_WAVE * J] = U.st.cum;
+    auto &stage_code = U.st.code;
+    __shared__ uint32_t s_flag;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += kThreads)
+        binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
+    __syncthreads();
+    WaveStats ws = {0, 0};
+    const uint32_t G = S.groups;
+    const uint32_t q = blockIdx.x / G, g = blockIdx.x - q * G;
+    if (q < S.nq && A.qb.k[q] != 0) {
+        uint32_t *step_cnt = S.step_cnt + (uint64_t)q * (A.t_all + 1);
+        // masks of one pass of all the query's waves: small steps run
+        // together in windows of at most one pass
+        const uint32_t pass = MIH_WAVE * J, cap = G * kW * pass;
+        auto masks_of = [&](uint32_t u) {
+            const uint32_t r = u / A.m;
+            return binom[A.tables[u - r * A.m].len][r];   // 0 when r' > s: the step covers radius u all the same
+        };
+        // expected candidates of a step (uniform codes: n / 2^s per bucket, at
+        // least one): a window keeps them to a quarter of the query's buffer,
+        // since the bound tau only falls once k codes have been found
+        auto cands_of = [&](uint32_t u) {
+            const uint32_t len = A.tables[u % A.m].len;
+            const uint64_t per = len >= 64 ? 0 : A.n >> len;
+            return (uint64_t)masks_of(u) * (per > 1 ? per : 1);
+        };
+        const uint64_t cand_cap = A.qb.cap[q] / 4;
+        constexpr uint32_t kNone = 0xFFFFFFFFu;
+        for (uint32_t t = 0, prev_tw = kNone, prev2_tw = kNone;;) {
+            // the window t .. tw: every step up to a pass of masks in all (at
+            // least step t), the same for every workgroup of the query
+            uint32_t tw = t, total = masks_of(t);
+            uint64_t cands = cands_of(t);
+            while (tw < A.t_all && total + masks_of(tw + 1) <= cap && cands + cands_of(tw + 1) <= cand_cap) {
+                ++tw;
+                total += masks_of(tw);
+                cands += cands_of(tw);
+            }
+            // A workgroup runs at most one window ahead of the completed
+            // ones: before a window it waits, a bounded number of polls, for
+            // the window before the previous one to complete (or the query to
+            // stop), and before a window larger than one pass of the query's
+            // waves for the previous one.  Without it, workgroups with no
+            // share of the small early windows would run far ahead, into
+            // steps past the stop, with the bound still loose.  Past the
+            // bound a workgroup goes on, which is only speculation.
+            const uint32_t need = total > cap ? prev_tw : prev2_tw;
+            if (need != kNone) {
+                if (tid == 0) {
+                    for (uint32_t i = 0; i < kSmallPolls; ++i) {
+                        if (load_relaxed(step_cnt + need) >= G || load_relaxed(S.stop + q) != kNone) break;
+                        __builtin_amdgcn_s_sleep(8);
+                    }
+                }
+                __syncthreads();
+            }
+            // the query's stop flag, seen at every window boundary
+            if (tid == 0) s_flag = load_relaxed(S.stop + q);
+            __syncthreads();
+            const bool stopped = s_flag != kNone;
+            __syncthreads();   // s_flag is rewritten below
+            if (stopped) break;
+            // contiguous ranges of whole passes over the window's masks, one per wave
+            const uint32_t per = ((total + G * kW - 1) / (G * kW) + pass - 1) / pass * pass;
+            const uint32_t rb = (g * kW + wave) * per;
+            const uint32_t re = rb + per < total ? rb + per : total;
+            uint32_t base = 0;
+            for (uint32_t u = t; u <= tw && base < re; ++u) {
+                const uint32_t M = masks_of(u);
+                const uint32_t lo = rb > base ? rb - base : 0u, hi = re - base < M ? re - base : M;
+                if (lo < hi) {
+                    const uint32_t rp = u / A.m, a = u - rp * A.m;
+                    uint64_t gq[W];
+                    process_step<W, TM, INLINE, J>(A, q, u, query_key<W>(A, q, a, gq), A.tables[a].len, rp, lo, hi,
+                                                   binom, stage_pos[wave], stage_cum[wave], stage_code[wave], ws);
+                }
+                base += M;
+            }
+            __syncthreads();   // this workgroup's share of the window is done
+            if (tid == 0) {
+                __threadfence();   // its candidates and counts before the step count
+                s_flag = atomicAdd(step_cnt + tw, 1u) + 1 == G ? 1u : 0u;
+                __threadfence();
+            }
+            __syncthreads();
+            const bool last = s_flag != 0;
+            __syncthreads();
+            if (last) {
+                // every workgroup has finished steps 0 .. tw: every code within
+                // distance tw has been found.  Algorithm 3 stops after step
+                // tau when tau <= tw (no earlier window reached tau), or
+                // after the last step
+                if (wave == 0) {
+                    uint32_t tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
+                    tau = tighten_tau(A.qb, q, tau);
+                    uint32_t stop = 0xFFFFFFFFu;
+                    if (tau <= tw) stop = tau > t ? tau : t;
+                    else if (tw >= A.t_all) stop = tw;
+                    if (lane == 0) s_flag = stop;
+                }
+                __syncthreads();
+                const uint32_t stop = s_flag;
+                if (stop != 0xFFFFFFFFu && tid == 0) atomicMin(S.stop + q, stop);
+                __syncthreads();
+                if (stop != 0xFFFFFFFFu) break;
+            } else if (tw >= A.t_all) {
+                break;   // the last step: its last finisher raises the flag
+            }
+            prev2_tw = prev_tw;
+            prev_tw = tw;
+            t = tw + 1;
+        }
+        // the workgroup that leaves last writes the rows
+        if (tid == 0) {
+            __threadfence();
+            s_flag = atomicAdd(S.exits + q, 1u) + 1 == G ? 1u : 0u;
+            __threadfence();
+        }
+        __syncthreads();
+        if (s_flag) {
+            const uint32_t cnt = load_relaxed(A.qb.count + q);
+            if (tid == 0) {
+                atomicAdd(&A.stats[2], (unsigned long long)load_relaxed(S.stop + q) + 1);   // steps
+                atomicAdd(&A.stats[3], (unsigned long long)cnt);                            // appended
+            }
+            if (cnt > A.qb.cap[q]) {
+                if (tid == 0) S.ovf_list[atomicAdd(S.ovf_count, 1u)] = q;
+            } else {
+                finalize_one(A.qb, q, S.out_ids + S.row_off[q], S.out_dists + S.row_off[q], U.fin);
+            }
+        }
+    }
+    if (lane == 0) {
+        atomicAdd(&A.stats[0], (unsigned long long)ws.probes);
+        atomicAdd(&A.stats[1], (unsigned long long)ws.candidates);
+    }
+}
+
 // After a round: termination test for the step each active query just
 // finished, and the next non-empty step for the others (a shell is empty
 // when r' exceeds the substring length).  Finished queries go to the done
@@ -770,6 +1301,25 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
     if (D < tau) { A.qb.tau[q] = D; tau = D; }
     uint32_t t = A.t[q];
     uint32_t out = 0xFFFFFFFFu;
+    if (A.quantum_items) {
+        // a step cut by the work quantum: its next portion in the next round
+        // (the step is not complete, so no termination test yet)
+        const uint32_t rp = t / A.m;
+        uint32_t M = 0;
+        if (rp <= A.tables[t - rp * A.m].len) {
+            const uint32_t s = A.tables[t - rp * A.m].len;
+            uint64_t c = 1;
+            for (uint32_t i = 1; i <= rp; ++i) c = c * (s - rp + i) / i;
+            M = (uint32_t)c;
+        }
+        const uint32_t it = (M + A.chunk - 1) / A.chunk;
+        if (A.cursor[q] + A.quantum_items < it) {
+            A.cursor[q] += A.quantum_items;
+            A.next_t[i] = t;
+            return;
+        }
+        A.cursor[q] = 0;
+    }
     // after step t every code within distance t has been found (Prop. 2);
     // an approximate query also stops at its step limit or candidate budget
     const uint32_t max_t = A.max_t[q], budget = A.budget[q];
@@ -811,18 +1361,22 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
 // the group then resumes after its window's last step.
 __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
 {
-    // [nbins] counts, [nbins] cursors, [nbins] window ends, then per group
-    // (at most one per bin) its first step, query count, items per query
-    // and steps taken: the serial part below works in LDS only
+    // Bins: two per step, 2 t for a portion of step t that the work quantum
+    // leaves unfinished, 2 t + 1 for the portion that finishes it (or the
+    // whole step).  [nbins] counts, [nbins] cursors, [nbins] window ends,
+    // then per group (at most one per bin) its first step, query count,
+    // items per query and steps taken: the serial part below works in LDS
+    // only.
     extern __shared__ uint32_t bins[];
     __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
     __shared__ uint32_t s_active, s_groups;
     __shared__ unsigned long long s_items, s_sweep;
     const uint32_t tid = threadIdx.x;
-    const uint32_t nbins = A.t_all + 1;
+    const uint32_t nbins = 2 * (A.t_all + 1);
     mih::Control *ctrl = A.ctrl;
     const uint32_t n_old = ctrl->n_active;
     const uint32_t n_new = ctrl->n_new;
+    const uint32_t Qi = A.quantum_items;
     uint32_t *last = bins + 2 * nbins;
     uint32_t *g_t = bins + 3 * nbins, *g_count = bins + 4 * nbins;
     uint32_t *g_ipq = bins + 5 * nbins, *g_steps = bins + 6 * nbins;
@@ -830,11 +1384,22 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
     for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += 1024)
         binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
     __syncthreads();
+    // items of step t, and whether a query with `cur` of them done finishes
+    // the step in this round
+    auto items_of = [&](uint32_t t) {
+        const uint32_t rp = t / A.m;
+        const uint32_t M = binom[A.tables[t - rp * A.m].len][rp];
+        return (M + A.chunk - 1) / A.chunk;
+    };
+    auto bin_of = [&](uint32_t t, uint32_t q) {
+        const bool fin = Qi == 0 || A.cursor[q] + Qi >= items_of(t);
+        return 2 * t + (fin ? 1u : 0u);
+    };
     for (uint32_t i = tid; i < n_old; i += 1024) {
-        uint32_t nt = A.next_t[i];
-        if (nt != 0xFFFFFFFFu) atomicAdd(&bins[nt], 1u);
+        const uint32_t nt = A.next_t[i];
+        if (nt != 0xFFFFFFFFu) atomicAdd(&bins[bin_of(nt, A.active[i])], 1u);
     }
-    if (tid == 0) atomicAdd(&bins[0], n_new);
+    for (uint32_t i = tid; i < n_new; i += 1024) atomicAdd(&bins[bin_of(0, A.new_slots[i])], 1u);
     __syncthreads();
     if (tid == 0) {
         uint32_t slot = 0, ng = 0;
@@ -842,39 +1407,48 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
         for (uint32_t b = 0; b < nbins; ++b) {
             uint32_t c = bins[b];
             bins[nbins + b] = slot;
-            last[b] = b;
+            last[b] = b >> 1;
             if (!c) continue;
-            const uint32_t rp = b / A.m;
-            const uint32_t s = A.tables[b - rp * A.m].len;
+            const uint32_t t = b >> 1, fin = b & 1u;
+            const uint32_t rp = t / A.m;
+            const uint32_t s = A.tables[t - rp * A.m].len;
             const uint32_t M = binom[s][rp];
+            const uint32_t it = (M + A.chunk - 1) / A.chunk;
             // many probes per bucket line: run the step partition by
-            // partition (sweep kernel; no items of the round kernel)
+            // partition (sweep kernel; no items of the round kernel); the
+            // quantum cuts steps into portions of Qi items, the final one
+            // holding what is left after the whole portions
             const bool sweep = A.sweep_shift != 0 && s >= mih::kSweepMinBits &&
                                (uint64_t)c * M >= ((1ull << s) >> A.sweep_shift);
-            const uint32_t ipq = sweep ? 0u : (M + A.chunk - 1) / A.chunk;
-            g_t[ng] = b;
+            uint32_t ipq = it;
+            if (Qi) ipq = fin ? it - (it ? (it - 1) / Qi * Qi : 0u) : Qi;
+            if (sweep) ipq = 0;
+            g_t[ng] = t;
             g_count[ng] = c;
             g_ipq[ng] = ipq;
             g_steps[ng] = 1;
             A.groups[ng].step_items[0] = 0;
             A.groups[ng].step_items[1] = ipq;
             A.groups[ng].slot_start = slot;
+            A.groups[ng].final = fin;
             ++ng;
             slot += c;
             items += (uint64_t)c * ipq;
-            masks += (uint64_t)c * M;
+            masks += (uint64_t)c * (sweep ? M : (uint64_t)ipq * A.chunk);
         }
-        // lookahead: pass u offers step t + u to every group that took all
-        // of its steps so far, while the round's items and masks fit
+        // lookahead: pass u offers step t + u to every group that finishes
+        // its step and took all of its steps so far, while the round's items
+        // and masks fit (and, under a quantum, while the step fits in one)
         for (uint32_t u = 1; u < A.look_max && items < A.look_items && masks < A.look_masks; ++u) {
             bool grew = false;
             for (uint32_t x = 0; x < ng; ++x) {
-                if (g_ipq[x] == 0 || g_steps[x] != u) continue;   // swept, or stopped growing
+                if (g_ipq[x] == 0 || g_steps[x] != u || !A.groups[x].final) continue;
                 const uint32_t tn = g_t[x] + u;
                 if (tn > A.t_all) continue;
                 const uint32_t rp = tn / A.m;
                 const uint32_t M = binom[A.tables[tn - rp * A.m].len][rp];
                 const uint32_t ni = (M + A.chunk - 1) / A.chunk;
+                if (Qi && ni > Qi) continue;
                 const uint64_t c = g_count[x];
                 if (items + c * ni > A.look_items || masks + c * M > A.look_masks) continue;
                 items += c * ni;
@@ -882,7 +1456,7 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
                 g_ipq[x] += ni;
                 g_steps[x] = u + 1;
                 A.groups[x].step_items[u + 1] = g_ipq[x];
-                last[g_t[x]] = tn;
+                last[2 * g_t[x] + 1] = tn;
                 grew = true;
             }
             if (!grew) break;
@@ -902,11 +1476,13 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
             G.sweep_bits = 0;
             G.sweep_qc = 0;
             if (g_ipq[x] == 0) {
-                // at least kSweepXcds partitions: one share per XCD
+                // at least kSweepXcds partitions: one share per XCD; the
+                // partition kernel stages a partition's occupancy bits in LDS
                 const uint32_t rp = g_t[x] / A.m;
                 const uint32_t s = A.tables[g_t[x] - rp * A.m].len;
-                const uint32_t L = A.sweep_bits < s - 3 ? A.sweep_bits : s - 3;
-                const uint32_t qc = (g_count[x] + mih::kSweepQueries - 1) / mih::kSweepQueries;
+                const uint32_t Lmax = A.sweep_part ? A.part_bits : A.sweep_bits;
+                const uint32_t L = Lmax < s - 3 ? Lmax : s - 3;
+                const uint32_t qc = (g_count[x] + A.sweep_q - 1) / A.sweep_q;
                 G.sweep_bits = L;
                 G.sweep_qc = qc;
                 sweep_items += ((1ull << (s - L)) / mih::kSweepXcds) * qc;   // per XCD
@@ -919,18 +1495,23 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
     }
     __syncthreads();
     // a query whose group runs ahead resumes after the window's last step
+    // (its cursor still counts the items of the window's first step, which
+    // the round kernel needs; the window's later steps fit in one quantum,
+    // so the advance kernel finds the last one finished whatever the cursor)
     for (uint32_t i = tid; i < n_old; i += 1024) {
-        uint32_t nt = A.next_t[i];
+        const uint32_t nt = A.next_t[i];
         if (nt != 0xFFFFFFFFu) {
             const uint32_t q = A.active[i];
-            A.active_tmp[atomicAdd(&bins[nbins + nt], 1u)] = q;
-            if (last[nt] != nt) A.t[q] = last[nt];
+            const uint32_t b = bin_of(nt, q);
+            A.active_tmp[atomicAdd(&bins[nbins + b], 1u)] = q;
+            if (last[b] != nt) A.t[q] = last[b];
         }
     }
     for (uint32_t i = tid; i < n_new; i += 1024) {
         const uint32_t q = A.new_slots[i];
-        A.active_tmp[atomicAdd(&bins[nbins], 1u)] = q;
-        if (last[0] != 0) A.t[q] = last[0];
+        const uint32_t b = bin_of(0, q);
+        A.active_tmp[atomicAdd(&bins[nbins + b], 1u)] = q;
+        if (last[b] != 0) A.t[q] = last[b];
     }
     __syncthreads();
     const uint32_t total = s_active;
@@ -966,6 +1547,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_admit_kernel(mih::MihArgs A, co
     A.qb.tau[q] = r.tau0;
     A.qb.count[q] = 0;
     A.t[q] = 0;
+    A.cursor[q] = 0;
     A.max_t[q] = r.max_t;
     A.budget[q] = r.budget;
     A.uniq[q] = 0;
@@ -976,54 +1558,67 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_admit_kernel(mih::MihArgs A, co
     A.new_slots[i] = q;
 }
 
+// Which kernel: the round kernel, the sweep kernel, or the partition
+// kernel (the sweep of tables with an occupancy map).
+enum { K_ROUND = 0, K_SWEEP = 1, K_PART = 2, K_SMALL = 3 };
+
 // Kernel for (W, table mode, codes mode, J); J must be 4, 8 or 16.
 template <int W, int TM, bool INLINE, int J>
-const void *kernel_of(bool sweep)
+const void *kernel_of(int which)
 {
-    return sweep ? reinterpret_cast<const void *>(&mih_sweep_kernel<W, TM, INLINE, J>)
-                 : reinterpret_cast<const void *>(&mih_round_kernel<W, TM, INLINE, J>);
+    if (which == K_PART) {
+        if constexpr (TM == mih::TM_DIRECT || TM == mih::TM_HEADS)
+            return reinterpret_cast<const void *>(&mih_part_kernel<W, TM, INLINE, J>);
+        return nullptr;
+    }
+    if (which == K_SMALL) return reinterpret_cast<const void *>(&mih_small_kernel<W, TM, INLINE, J>);
+    return which == K_SWEEP ? reinterpret_cast<const void *>(&mih_sweep_kernel<W, TM, INLINE, J>)
+                            : reinterpret_cast<const void *>(&mih_round_kernel<W, TM, INLINE, J>);
 }
 
 template <int W, int TM, bool INLINE>
-const void *round_kernel_ptr(uint32_t J, bool sweep)
+const void *round_kernel_ptr(uint32_t J, int which)
 {
     switch (J) {
-    case 4: return kernel_of<W, TM, INLINE, 4>(sweep);
-    case 8: return kernel_of<W, TM, INLINE, 8>(sweep);
-    case 16: return kernel_of<W, TM, INLINE, 16>(sweep);
+    case 4: return kernel_of<W, TM, INLINE, 4>(which);
+    case 8: return kernel_of<W, TM, INLINE, 8>(which);
+    case 16: return kernel_of<W, TM, INLINE, 16>(which);
     default: return nullptr;
     }
 }
 
 template <int W>
-const void *round_kernel_w(uint32_t tm, bool inline_codes, uint32_t J, bool sweep)
+const void *round_kernel_w(uint32_t tm, bool inline_codes, uint32_t J, int which)
 {
     switch (tm) {
     case mih::TM_DIRECT:
-        return inline_codes ? round_kernel_ptr<W, mih::TM_DIRECT, true>(J, sweep)
-                            : round_kernel_ptr<W, mih::TM_DIRECT, false>(J, sweep);
+        return inline_codes ? round_kernel_ptr<W, mih::TM_DIRECT, true>(J, which)
+                            : round_kernel_ptr<W, mih::TM_DIRECT, false>(J, which);
     case mih::TM_SORTED:
-        return inline_codes ? round_kernel_ptr<W, mih::TM_SORTED, true>(J, sweep)
-                            : round_kernel_ptr<W, mih::TM_SORTED, false>(J, sweep);
+        return inline_codes ? round_kernel_ptr<W, mih::TM_SORTED, true>(J, which)
+                            : round_kernel_ptr<W, mih::TM_SORTED, false>(J, which);
     case mih::TM_GROUPED:   // the group scan reads the codes in table order
-        return inline_codes ? round_kernel_ptr<W, mih::TM_GROUPED, true>(J, sweep) : nullptr;
+        return inline_codes ? round_kernel_ptr<W, mih::TM_GROUPED, true>(J, which) : nullptr;
     case mih::TM_HEADS:     // 64-bit codes in table order only
-        if constexpr (W == 1) return inline_codes ? round_kernel_ptr<W, mih::TM_HEADS, true>(J, sweep) : nullptr;
+        if constexpr (W == 1) return inline_codes ? round_kernel_ptr<W, mih::TM_HEADS, true>(J, which) : nullptr;
         return nullptr;
     default: return nullptr;
     }
 }
 
-const void *round_kernel(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, bool sweep = false)
+const void *round_kernel(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, int which = K_ROUND)
 {
     switch (W) {
-    case 1: return round_kernel_w<1>(tm, inline_codes, J, sweep);
-    case 2: return round_kernel_w<2>(tm, inline_codes, J, sweep);
-    case 3: return round_kernel_w<3>(tm, inline_codes, J, sweep);
-    case 4: return round_kernel_w<4>(tm, inline_codes, J, sweep);
+    case 1: return round_kernel_w<1>(tm, inline_codes, J, which);
+    case 2: return round_kernel_w<2>(tm, inline_codes, J, which);
+    case 3: return round_kernel_w<3>(tm, inline_codes, J, which);
+    case 4: return round_kernel_w<4>(tm, inline_codes, J, which);
     default: return nullptr;
     }
 }
+
+// Dynamic LDS of the partition kernel: the occupancy bits of one partition.
+size_t part_lds_bytes(uint32_t part_bits) { return ((size_t)1 << part_bits) / 8; }
 
 }  // namespace
 
@@ -1033,7 +1628,7 @@ bool mih_probes_per_lane_ok(uint32_t J) { return J == 4 || J == 8 || J == 16; }
 
 hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s)
 {
-    const void *k = round_kernel(A.W, A.tm, A.inline_codes, A.J);
+    const void *k = round_kernel(A.W, A.tm, A.inline_codes, A.J, K_ROUND);
     if (!k) return hipErrorInvalidValue;
     void *args[] = {const_cast<MihArgs *>(&A)};
     return hipLaunchKernel(k, dim3(grid), dim3(MIH_BLOCK), args, 0, s);
@@ -1041,17 +1636,37 @@ hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s)
 
 hipError_t mih_sweep(const MihArgs &A, uint32_t grid, hipStream_t s)
 {
-    const void *k = round_kernel(A.W, A.tm, A.inline_codes, A.J, true);
+    const void *k = round_kernel(A.W, A.tm, A.inline_codes, A.J, A.sweep_part ? K_PART : K_SWEEP);
     if (!k) return hipErrorInvalidValue;
     void *args[] = {const_cast<MihArgs *>(&A)};
-    return hipLaunchKernel(k, dim3(grid), dim3(MIH_BLOCK), args, 0, s);
+    const size_t lds = A.sweep_part ? part_lds_bytes(A.part_bits) : 0;
+    return hipLaunchKernel(k, dim3(grid), dim3(MIH_BLOCK), args, lds, s);
 }
 
-int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, bool sweep)
+hipError_t mih_small(const MihArgs &A, const SmallArgs &S, hipStream_t s)
 {
-    const void *k = round_kernel(W, tm, inline_codes, J, sweep);
+    const void *k = round_kernel(A.W, A.tm, A.inline_codes, A.J, K_SMALL);
+    if (!k) return hipErrorInvalidValue;
+    MihArgs a = A;
+    SmallArgs b = S;
+    void *args[] = {&a, &b};
+    const uint32_t block = (A.J >= 16 ? 4u : (A.J >= 8 ? 8u : 16u)) * MIH_WAVE;   // small_waves<J>() waves
+    return hipLaunchKernel(k, dim3(S.nq * S.groups), dim3(block), args, 0, s);
+}
+
+bool mih_part_kernel_ok(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J)
+{
+    return round_kernel(W, tm, inline_codes, J, K_PART) != nullptr;
+}
+
+int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, int which,
+                        uint32_t part_bits)
+{
+    const void *k = round_kernel(W, tm, inline_codes, J, which);
+    const size_t lds = which == K_PART ? part_lds_bytes(part_bits) : 0;
+    const int block = which == K_SMALL ? (J >= 16 ? 4 : (J >= 8 ? 8 : 16)) * MIH_WAVE : MIH_BLOCK;
     int blocks = 0;
-    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, MIH_BLOCK, 0) != hipSuccess) {
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, block, lds) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
@@ -1060,7 +1675,7 @@ int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, 
 
 hipError_t mih_regroup(const MihArgs &A, hipStream_t s)
 {
-    const size_t lds = sizeof(uint32_t) * 7 * (A.t_all + 1);
+    const size_t lds = sizeof(uint32_t) * 7 * 2 * (A.t_all + 1);
     mih_regroup_kernel<<<1, 1024, lds, s>>>(A);
     return hipGetLastError();
 }

@@ -1,6 +1,6 @@
 """Running queries ahead by several steps per round (lookahead) changes
 neither exact kNN nor r-neighbour results, and small batches then finish in
-fewer rounds.  Every result is checked against the oracle's plain linear
+fewer rounds (device rounds: the one-launch path for small batches is off).  Every result is checked against the oracle's plain linear
 scan, bit for bit."""
 import numpy as np
 import pytest
@@ -37,7 +37,7 @@ def test_lookahead_exact_knn(mih, bits, m, kind, tmode, cmode):
     oi, od = oracle.knn(codes, queries, ks)
     runs = {}
     for look in (1, 2, 5, 16, 32):
-        idx.set_tuning(lookahead=look)
+        idx.set_tuning(lookahead=look, small_batch=0)
         ids, dists, st = idx.knn(dq, ks.tolist(), stats=True)
         assert_same(ids, dists, oi, od, f"{bits}/{m}/{tmode}/{cmode} look={look}")
         runs[look] = st
@@ -57,7 +57,7 @@ def test_lookahead_k_beyond_n(mih):
     dq = to_dev(queries)
     oi, od = oracle.knn(codes, queries, k)
     for look in (1, 16, 32):
-        idx.set_tuning(lookahead=look)
+        idx.set_tuning(lookahead=look, small_batch=0)
         ids, dists = idx.knn(dq, k)
         assert_same(ids, dists, oi, od, f"k > n look={look}")
     idx.close()
@@ -72,9 +72,9 @@ def test_lookahead_cuts_rounds_of_a_small_batch(mih):
     idx = mih.build(to_dev(codes), m)
     dq = to_dev(queries)
     oi, od = oracle.knn(codes, queries, k)
-    idx.set_tuning(lookahead=1)
+    idx.set_tuning(lookahead=1, small_batch=0)
     _, _, st1 = idx.knn(dq, k, stats=True)
-    idx.set_tuning(lookahead=16)
+    idx.set_tuning(lookahead=16, small_batch=0)
     ids, dists, st16 = idx.knn(dq, k, stats=True)
     assert_same(ids, dists, oi, od, "look=16")
     assert st16["rounds"] < st1["rounds"], (st1, st16)
@@ -87,7 +87,7 @@ def test_lookahead_rnn(mih):
     queries = datagen.uniform_codes(nq, 64, 404)
     idx = mih.build(to_dev(codes), 3)
     dq = to_dev(queries)
-    idx.set_tuning(lookahead=16)
+    idx.set_tuning(lookahead=16, small_batch=0)
     off, ids, dists = idx.rnn(dq, r)
     for i in range(nq):
         ri, rd = oracle.rnn(codes, queries[i], r)
@@ -107,7 +107,7 @@ def test_lookahead_leaves_approximate_search_alone(mih):
     dq = to_dev(queries)
     out = {}
     for look in (1, 16):
-        idx.set_tuning(lookahead=look)
+        idx.set_tuning(lookahead=look, small_batch=0)
         out[look] = idx.knn_approx(dq, k, max_radius=6, stats=True)
     assert np.array_equal(out[1][0].cpu().numpy(), out[16][0].cpu().numpy())
     assert np.array_equal(out[1][1].cpu().numpy(), out[16][1].cpu().numpy())
@@ -120,8 +120,8 @@ def test_lookahead_tuning_is_validated(mih):
     idx = mih.build(to_dev(codes), 2)
     for bad in (0, 33):
         with pytest.raises(mih.MihError):
-            idx.set_tuning(lookahead=bad)
+            idx.set_tuning(lookahead=bad, small_batch=0)
     assert idx.get_tuning()["lookahead"] == 16
-    idx.set_tuning(lookahead=32)
+    idx.set_tuning(lookahead=32, small_batch=0)
     assert idx.get_tuning()["lookahead"] == 32
     idx.close()

@@ -100,18 +100,25 @@ def test_mih_launch_tunings_agree(mih, tmode, occ, shift):
     lens, _ = formulas.partition(64, m)
     dk = od.reshape(nq, k)[:, -1]
     probes = sum(sum(formulas.shell(lens[t % m], t // m) for t in range(int(d) + 1)) for d in dk)
+    # tables with an occupancy map sweep in the partition kernel, whose
+    # work items take sweep_queries queries each
+    part = shift and occ and tmode in ("direct", "heads")
     for J in (4, 8, 16):
         for chunk in (64 * J * 2, 64 * J * 32):
-            for sbits in ((16, 20) if shift else (18,)):
+            for sbits in ((12, 16, 20) if shift else (18,)):
                 for look in (1, 16):
-                    idx.set_tuning(J, chunk, 0, occ, shift, sbits, look)
-                    ids, dists, st = idx.knn(dq, k, stats=True)
-                    what = f"{tmode} occ={occ} sweep={shift}/{sbits} J={J} chunk={chunk} look={look}"
-                    assert_same(ids, dists, oi, od, what)
-                    if look == 1:
-                        assert st["probes"] == probes, what
-                    else:
-                        assert st["probes"] >= probes, what
+                    for sq in ((64, 192, 1024) if part else (256,)):
+                        idx.set_tuning(probes_per_lane=J, chunk=chunk, blocks_per_cu=0, occupancy_filter=occ,
+                                       sweep_shift=shift, sweep_bits=sbits, lookahead=look, sweep_queries=sq,
+                                       small_batch=0)   # device rounds, not the one-launch path
+                        ids, dists, st = idx.knn(dq, k, stats=True)
+                        what = (f"{tmode} occ={occ} sweep={shift}/{sbits}/{sq} J={J} chunk={chunk} "
+                                f"look={look}")
+                        assert_same(ids, dists, oi, od, what)
+                        if look == 1:
+                            assert st["probes"] == probes, what
+                        else:
+                            assert st["probes"] >= probes, what
     idx.close()
 
 
@@ -149,7 +156,8 @@ def test_mih_probe_count_equals_closed_form(mih):
     codes = datagen.uniform_codes(n, 64, 11)
     queries = datagen.uniform_codes(nq, 64, 12)
     idx = mih.build(to_dev(codes), m)
-    idx.set_tuning(lookahead=1)   # one step per round: no step runs early
+    # one step per round in device rounds: no step runs early
+    idx.set_tuning(lookahead=1, small_batch=0)
     ids, dists, st = idx.knn(to_dev(queries), k, stats=True)
     oi, od = oracle.knn(codes, queries, k)
     assert_same(ids, dists, oi, od, "probe count run")

@@ -50,6 +50,10 @@ def draw(rng):
     tuning = dict(probes_per_lane=J, chunk=64 * J * int(rng.choice([1, 2, 8])), blocks_per_cu=0,
                   occupancy_filter=int(rng.integers(0, 2)), sweep_shift=int(rng.choice([0, 0, 9])),
                   sweep_bits=18, lookahead=int(rng.choice([1, 3, 16, 32])))
+    # partition size and queries per item of the sweeps, from the draws so far
+    tuning["sweep_bits"] = (12, 16, 18)[m % 3]
+    tuning["sweep_queries"] = 64 * (1 + (7 * J + m) % 6)
+    tuning["small_batch"] = (0, 512)[m % 2]   # device rounds, or one launch for these small batches
     return dict(bits=bits, W=W, m=m, tmode=tmode, cmode=cmode, inline_tables=inline_tables, n=n, nq=nq,
                 kind=kind, tuning=tuning)
 

@@ -116,3 +116,40 @@ def test_server_overflow_rerun_in_mix(mih):
         ids, dists = srv.result(t)
         oi, od = oracle.knn(codes, qq, k)
         assert_same(ids, dists, oi, od, "overflow in server")
+
+
+def test_work_quantum_keeps_every_result(mih, setup):
+    # rounds that probe at most round_masks shell masks per query (a larger
+    # step continues over the following rounds from its saved position):
+    # batch and serving results are unchanged, the rounds more numerous
+    codes, pool, idx, reqs = setup
+    dpool = to_dev(pool)
+    base = idx.get_tuning()
+    ks = [k for _, _, kk in reqs for k in kk]
+    nq = len(ks)
+    idx.set_tuning(small_batch=0, round_masks=0)
+    ref_i, ref_d, ref_st = idx.knn(dpool[:nq], ks, stats=True)
+    oi, od = oracle.knn(codes, pool[:nq], np.array(ks, dtype=np.uint32))
+    assert_same(ref_i, ref_d, oi, od, "no quantum")
+    for J, chunk, rm, look in [(4, 256, 256, 1), (4, 256, 1000, 16), (8, 512, 5000, 16), (4, 1024, 1, 1)]:
+        idx.set_tuning(probes_per_lane=J, chunk=chunk, round_masks=rm, lookahead=look, small_batch=0)
+        ids, dists, st = idx.knn(dpool[:nq], ks, stats=True)
+        what = f"quantum {rm} chunk {chunk} look {look}"
+        assert torch.equal(ids, ref_i) and torch.equal(dists, ref_d), what
+        assert st["rounds"] > ref_st["rounds"], what
+    # serving with a quantum: every request as alone without one
+    idx.set_tuning(probes_per_lane=4, chunk=256, round_masks=512, lookahead=16)
+    srv = mih.Server(idx, max_queries=96, buffer_entries=96 * 3000)
+    tickets = []
+    for i, (off, size, kk) in enumerate(reqs[:20]):
+        tickets.append(srv.submit(dpool[off:off + size], kk))
+        if i % 2 == 1:
+            srv.step()
+    srv.drain()
+    koff = np.concatenate([[0], np.cumsum(ks)])   # row offset of each query of the batch
+    for (off, size, kk), t in zip(reqs[:20], tickets):
+        mi, md = srv.result(t)
+        a, b = int(koff[off]), int(koff[off + size])
+        assert torch.equal(mi.reshape(-1), ref_i[a:b]) and torch.equal(md.reshape(-1), ref_d[a:b])
+    srv.close()
+    idx.set_tuning(**base)

@@ -43,7 +43,7 @@ def test_knn_with_optimised_substrings(mih, bits, m, tmode, cmode):
     order = mih.optimize_substrings(dc, m, sample=50_000, first_bit=1)
     assert order == S.greedy_bit_order(S.cooccurrence(codes[:50_000]), 50_000, bits, m, 1)
     idx = mih.build(dc, m, table_mode=tmode, codes_mode=cmode, bit_order=order)
-    idx.set_tuning(lookahead=1)   # one step per round, for the probe count below
+    idx.set_tuning(lookahead=1, small_batch=0)   # one step per device round, for the probe count below
     assert idx.info()["bit_order"] == order
     for k in (1, 10, 100):
         ids, dists, st = idx.knn(dq, k, stats=True)
