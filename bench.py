@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--linscan-steps", type=int, default=None)
     ap.add_argument("--no-linscan", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=30.0,
                     help="wall-time budget of the CPU oracle sample")
     ap.add_argument("--threads", type=int, default=None, help="host threads for generation/oracle")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch tuning")
@@ -60,10 +60,13 @@ def parse():
                     help="queries the autotuner times (default: as many as the timed batch); "
                          "they are the rows of the query stream that follow the timed ones")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
-    ap.add_argument("--serve-requests", type=int, default=1000)
-    ap.add_argument("--serve-warmup", type=int, default=100)
-    ap.add_argument("--serve-loads", default="0.5,0.9",
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9",
                     help="fractions of the closed-loop capacity to replay the stream at")
+    ap.add_argument("--serve-quantum", type=int, default=1 << 20,
+                    help="serving leg: most shell masks a query probes per device round "
+                         "(round_masks; 0: whole steps)")
     ap.add_argument("--serve-slots", type=int, default=16384)
     ap.add_argument("--serve-tuning", default="",
                     help="launch tuning fields for the serving leg only, e.g. chunk=8192,lookahead=1 "
@@ -85,6 +88,11 @@ def parse():
                          "(the device's random-line rate, a ceiling for the search kernel)")
     ap.add_argument("--copy-calib", type=float, default=0.0,
                     help="also run one plain device copy of this many GiB (counter calibration)")
+    ap.add_argument("--line-calib", type=float, default=0.0,
+                    help="also run 2^28 random line reads from an array of this many GiB "
+                         "(counter calibration of random reads)")
+    ap.add_argument("--no-line-ceiling", action="store_true",
+                    help="skip the measurement of the device's random-line rate")
     return ap.parse_args()
 
 
@@ -121,11 +129,14 @@ def to_device(codes: np.ndarray, chunk_rows: int = 1 << 24):
 
 
 def counter_traffic(counters_file, tuning, modes):
-    """HBM bytes per launch of the search kernel from committed rocprofv3
-    counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a
-    plain copy of known size), or None when the kernel source, the launch
-    tuning or the table and codes modes differ from those of the counter
-    runs, or no counters exist for this workload."""
+    """HBM bytes per launch (device round) of the search from committed
+    rocprofv3 counter runs: (bytes, record) for the record whose launch
+    tuning matches, or (None, file contents) when the kernel sources or the
+    table and codes modes differ from those of the counter runs or no record
+    has this tuning, (None, None) when no counters exist for this workload.
+    FETCH_SIZE is scaled by its reading for a kernel of known count of random
+    64-byte line reads (the search's kind of read), WRITE_SIZE by its reading
+    for a plain copy of known size."""
     import hashlib
     path = os.path.join(ROOT, "profiles", counters_file)
     if not os.path.exists(path):
@@ -136,14 +147,69 @@ def counter_traffic(counters_file, tuning, modes):
         h.update(open(os.path.join(ROOT, src), "rb").read())
     if h.hexdigest()[:16] != rec["source_sha256_16"]:
         return None, rec
-    if any(tuning.get(k) != v for k, v in rec.get("tuning", {}).items()):
-        return None, rec
     if tuple(rec.get("modes", ())) != tuple(modes):   # the table and codes modes of the counter runs
         return None, rec
-    cal = rec["copy_calibration"]
-    fetch = np.mean(rec["fetch_kib_per_launch"]) * cal["fetch_factor"]
-    write = np.mean(rec["write_kib_per_launch"]) * cal["write_factor"]
-    return float((fetch + write) * 1024.0), rec
+    for r in rec["records"]:
+        if all(tuning.get(k) == v for k, v in r["tuning"].items()):
+            fetch = np.mean(r["fetch_kib_per_launch"]) * rec["random_line_calibration"]["fetch_factor"]
+            write = np.mean(r["write_kib_per_launch"]) * rec["copy_calibration"]["write_factor"]
+            return float((fetch + write) * 1024.0), r
+    return None, rec
+
+
+def search_roofline(st, info, n, bits, m, nq, ks, k_list, W, tuning):
+    """Roofline object of the multi-index search.  Algorithmic bytes per
+    call: 8 B per probed bucket (two 32-bit offsets; 12 B for SORTED tables:
+    directory and key), 4 B id + bits/8 B code per candidate, bits/8 B per
+    query and 8 B per output entry, over the HIP-event time of the call's
+    device rounds, against the 8 TB/s HBM peak.  Counter traffic from the
+    committed rocprofv3 runs of the same source and tuning, when they
+    exist."""
+    per_probe = 12 if info["table_mode"] == "sorted" else 8
+    per_cand = 4 + 8 * W
+    out_entries = int(np.sum(k_list, dtype=np.int64))
+    alg_bytes = (st["probes"] * per_probe + st["candidates"] * per_cand + nq * 8 * W + out_entries * 8)
+    kern_ms = st["search_kernel_ms"]
+    launches = max(1, st["search_launches"])
+    achieved = alg_bytes / (kern_ms / 1e3) / 1e9 if kern_ms > 0 else 0.0
+    traffic = None
+    lines = None
+    if (n, bits, m, nq, tuple(ks)) == (1_000_000_000, 64, 2, 10_000, (100,)):
+        traffic, rec = counter_traffic("mih_search_1e9x64_m2_k100_counters.json", tuning,
+                                       (info["table_mode"], info["codes_mode"]))
+        if traffic is not None:
+            # the reads are random 64 B lines; FETCH_SIZE counts each in full
+            per_launch = float(np.mean(rec["fetch_kib_per_launch"])) * 1024 / 64
+            lines = {"lines_per_launch": round(per_launch),
+                     "lines_per_s": round(per_launch / (kern_ms / launches / 1e3))}
+    return {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": round(traffic) if traffic is not None else None,
+        "traffic_unit": "bytes per launch: FETCH_SIZE scaled by the random-line calibration, "
+                        "WRITE_SIZE by the copy calibration",
+        "alg_bytes_per_launch": int(alg_bytes / launches),
+        "kernel": "device round (search kernels)", "launches_per_step": launches,
+        "avg_launch_ms": round(kern_ms / launches, 3),
+        "alg_bytes_per_step": int(alg_bytes),
+        "per_unit": {"probe_B": per_probe, "candidate_B": per_cand, "query_B": 8 * W, "output_entry_B": 8},
+        "probes_per_query": st["probes"] / nq, "candidates_per_query": st["candidates"] / nq,
+        "random_lines": lines,
+    }
+
+
+def cpu_description():
+    """Host CPU model, sockets and logical CPUs (from /proc/cpuinfo)."""
+    model, sockets = None, set()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name") and model is None:
+                model = line.split(":", 1)[1].strip()
+            elif line.startswith("physical id"):
+                sockets.add(line.split(":", 1)[1].strip())
+    except OSError:
+        pass
+    return {"cpu_model": model, "sockets": max(1, len(sockets)), "logical_cpus": os.cpu_count()}
 
 
 def serve_bench(mih, idx, kind, bits, k_choices, args, log_fn):
@@ -298,6 +364,16 @@ def main():
         log(f"copy calibration: {words * 8} bytes read and written")
         del a, b
 
+    if args.line_calib > 0:
+        # 2^28 random line reads of known count: the FETCH_SIZE counter of
+        # this kernel calibrates the counter for the search kernel's reads
+        arr = torch.ones(int(args.line_calib * 2**30) // 8, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        r = mih.random_read_rate(arr, 1 << 28, 8)
+        log(f"line calibration: {r['reads']} random line reads in {r['ms']:.2f} ms")
+        del arr
+        torch.cuda.synchronize()
+
     gather = None
     if args.gather_calib > 0:
         # independent random reads: every one touches its own line, as the
@@ -371,41 +447,31 @@ def main():
         vals, cnts = np.unique(r, return_counts=True)
         radius_hist[str(kv)] = {str(int(v)): int(c) for v, c in zip(vals, cnts)}
 
-    # ---------------- roofline of the search kernel
+    # ---------------- roofline of the search (one device round = one launch
+    # of the graph holding the search kernels)
     st = stats[-1]
-    # a candidate costs its code, plus its id where the table reads codes
-    # through the ids (MIXED: in that share of the tables, the tables being
-    # alike in expectation)
-    per_cand = 8 * W + 4 * (1 - info["inline_tables"] / m)
-    per_probe = 12 if info["table_mode"] == "sorted" else 8
-    alg_bytes = st["probes"] * per_probe + st["candidates"] * per_cand + st["appended"] * 16
-    kern_ms = st["search_kernel_ms"]
-    launches = max(1, st["search_launches"])
-    achieved = alg_bytes / (kern_ms / 1e3) / 1e9 if kern_ms > 0 else 0.0
-    traffic = None
-    lines = None
-    if (n, bits, m, nq, tuple(ks)) == (1_000_000_000, 64, 2, 10_000, (100,)):
-        traffic, rec = counter_traffic("mih_round_kernel_1e9x64_m2_k100_counters.json", idx.get_tuning(),
-                                       (info["table_mode"], info["codes_mode"]))
-        if traffic is not None:
-            # the reads are random 64 B lines, which FETCH_SIZE counts in full
-            per_launch = float(np.mean(rec["fetch_kib_per_launch"])) * 1024 / 64
-            lines = {"lines_per_launch": round(per_launch),
-                     "lines_per_s": round(per_launch / (kern_ms / launches / 1e3)),
-                     "plain_gather_reads_per_s": rec.get("random_read_calibration", {}).get("reads_per_s")}
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": round(traffic) if traffic is not None else None,
-        "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        "alg_bytes_per_launch": int(alg_bytes / launches),
-        "kernel": "mih_round_kernel", "launches_per_step": launches,
-        "avg_launch_ms": round(kern_ms / launches, 3),
-        "alg_bytes_per_step": int(alg_bytes),
-        "per_unit": {"probe_B": per_probe, "candidate_B": per_cand, "appended_B": 16},
-        "probes_per_query": st["probes"] / nq, "candidates_per_query": st["candidates"] / nq,
-        "random_lines": lines,
-    }
+    roofline = search_roofline(st, info, n, bits, m, nq, ks, k_list, W, idx.get_tuning())
+    ceiling = None
+    if not args.no_line_ceiling:
+        # the device's random-line rate, measured with several loads per lane
+        # in flight, over an array far larger than the caches
+        free = torch.cuda.mem_get_info()[0]
+        gib = min(16, max(1, int(free * 0.5) >> 30))
+        arr = torch.empty((gib << 30) // 8, dtype=torch.int64, device="cuda")
+        arr.fill_(1)
+        rr = [mih.random_read_rate(arr, 1 << 28, d) for d in (4, 8, 16)]
+        best = max(rr, key=lambda r: r["reads_per_s"])
+        ceiling = {"array_GiB": gib, "reads": best["reads"], "depth": best["depth"],
+                   "lines_per_s": round(best["reads_per_s"]),
+                   "kernel": "random_lines_kernel (mih_random_read_rate)"}
+        del arr
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log(f"random-line ceiling: {best['reads_per_s'] / 1e9:.1f} G lines/s (depth {best['depth']}, {gib} GiB)")
+        if roofline.get("random_lines"):
+            rl = roofline["random_lines"]
+            rl["ceiling_lines_per_s"] = ceiling["lines_per_s"]
+            rl["frac_of_ceiling"] = round(rl["lines_per_s"] / ceiling["lines_per_s"], 4)
 
     # ---------------- launch tunings (speed only; results must not change)
     sweep = None
@@ -522,8 +588,13 @@ def main():
             serve_k = (1, 10, 100)
         batch_t = idx.get_tuning()
         # rounds of a serving loop often hold few queries: smaller work items
-        # spread them over more waves (the batch-tuned chunk is for full batches)
-        serve_t = {"chunk": min(batch_t["chunk"], 8192)}
+        # spread them over more waves (the batch-tuned chunk is for full
+        # batches); a work quantum keeps the rounds short, so that a request
+        # arriving meanwhile does not wait for whole large steps of others;
+        # steps are not swept (a sweep runs whole steps); requests go through
+        # the rounds (the one-launch path is for mih_knn calls)
+        serve_t = {"chunk": min(batch_t["chunk"], 8192), "round_masks": args.serve_quantum,
+                   "sweep_shift": 0}
         if args.serve_tuning:
             serve_t = {f: int(v) for f, v in (kv.split("=") for kv in args.serve_tuning.split(","))}
         idx.set_tuning(**serve_t)
@@ -656,10 +727,23 @@ def main():
                            np.array_equal(od[o:o + kq_], gd[off[q]:off[q + 1]]))
                 o += kq_
             done += len(sel)
+        # the single-thread rate, for the paper's one-core regime: queries
+        # of the same subset one at a time on one thread, for about 3 s
+        one_done, one_spent = 0, 0.0
+        while one_done < nq and one_spent < 3.0:
+            q = order[one_done]
+            t = time.perf_counter()
+            oracle.knn(codes, queries[q:q + 1], k_list[q:q + 1], threads=1)
+            one_spent += time.perf_counter() - t
+            one_done += 1
         cpu = {"value": round(done / spent, 3), "unit": "queries/s", "cores": int(used),
                "kind": "oracle",
                "sample": f"{done} of the {nq} queries (seeded random subset) against all {n} codes, "
-                         f"same k; {spent:.1f} s wall on {used} host threads"}
+                         f"same k; {spent:.1f} s wall on {used} host threads",
+               "sample_queries": done, "threads": int(used),
+               "single_thread_value": round(one_done / one_spent, 4),
+               "single_thread_sample": f"{one_done} queries one at a time on 1 thread, {one_spent:.1f} s",
+               **cpu_description()}
         parity_oracle = {"queries_checked": done, "bit_exact": ok}
         log(f"oracle: {done} queries in {spent:.1f}s on {used} threads; MIH == oracle: {ok}")
         if rnn is not None:
@@ -675,6 +759,11 @@ def main():
             rnn["parity_with_oracle_2_queries"] = rok
             log(f"r-neighbours of 2 queries == oracle: {rok}")
 
+    # the headline latency: the 50% load level when it was run, else the first
+    headline_load = None
+    if serving and serving["loads"]:
+        half = [x for x in serving["loads"] if abs(x["load"] - 0.5) < 1e-9]
+        headline_load = half[0] if half else serving["loads"][0]
     out = {
         "metric": METRIC,
         "value": round(mih_qps, 1),
@@ -696,11 +785,10 @@ def main():
             "inline_tables": info["inline_tables"],
             "index_GiB": round(info["device_bytes"] / 2**30, 2), "build_ms": round(info["build_ms"], 1),
         },
-        "p50_ms": serving["loads"][0]["p50_ms"] if serving and serving["loads"] else None,
-        "p99_ms": serving["loads"][0]["p99_ms"] if serving and serving["loads"] else None,
+        "p50_ms": headline_load["p50_ms"] if headline_load else None,
+        "p99_ms": headline_load["p99_ms"] if headline_load else None,
         "latency_note": ("per request (arrival to last result), serving loop at "
-                         f"{serving['loads'][0]['load']:.0%} of closed-loop capacity" if serving and serving["loads"]
-                         else None),
+                         f"{headline_load['load']:.0%} of closed-loop capacity" if headline_load else None),
         "roofline": roofline,
         "serving": serving,
         "linscan": lin,
@@ -719,6 +807,7 @@ def main():
         "choose_m": chosen_m,
         "substring_optimisation": subopt,
         "random_read_calibration": gather,
+        "random_line_ceiling": ceiling,
         "mih_stats": {k_: (round(v, 3) if isinstance(v, float) else v) for k_, v in stats[-1].items()},
     }
     print(json.dumps(out), flush=True)

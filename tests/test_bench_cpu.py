@@ -37,21 +37,30 @@ def test_weighted_percentile_is_the_nearest_rank_of_the_expanded_list(seed):
 
 def test_counter_record_checks(tmp_path, monkeypatch):
     # a counter record of a made-up kernel source: traffic only while the
-    # source, the launch tuning and the table/codes modes all match
+    # source and the table/codes modes match and a record has the tuning
     import hashlib
     (tmp_path / "profiles").mkdir()
     (tmp_path / "k.hip").write_bytes(b"kernel source")
+    r1 = {"tuning": {"probes_per_lane": 8, "chunk": 16384}, "launches": 2,
+          "fetch_kib_per_launch": [10.0, 30.0], "write_kib_per_launch": [1.0, 3.0]}
+    r2 = {"tuning": {"probes_per_lane": 4, "chunk": 8192}, "launches": 2,
+          "fetch_kib_per_launch": [5.0, 5.0], "write_kib_per_launch": [1.0, 1.0]}
     rec = {"sources": ["k.hip"],
            "source_sha256_16": hashlib.sha256(b"kernel source").hexdigest()[:16],
-           "tuning": {"probes_per_lane": 8, "chunk": 16384}, "modes": ["heads", "inline"],
+           "modes": ["heads", "inline"],
            "copy_calibration": {"fetch_factor": 2.0, "write_factor": 1.0},
-           "fetch_kib_per_launch": [10.0, 30.0], "write_kib_per_launch": [1.0, 3.0]}
+           "random_line_calibration": {"fetch_factor": 1.01},
+           "records": [r1, r2]}
     (tmp_path / "profiles" / "c.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     tuning = {"probes_per_lane": 8, "chunk": 16384, "sweep_bits": 18}
     traffic, got = bench.counter_traffic("c.json", tuning, ("heads", "inline"))
-    assert traffic == (20.0 * 2.0 + 2.0 * 1.0) * 1024.0 and got == rec
-    assert bench.counter_traffic("c.json", dict(tuning, chunk=8192), ("heads", "inline"))[0] is None
+    # random reads scale by the random-line calibration, writes by the copy's
+    assert traffic == (20.0 * 1.01 + 2.0 * 1.0) * 1024.0 and got == r1
+    traffic, got = bench.counter_traffic("c.json", dict(tuning, probes_per_lane=4, chunk=8192),
+                                         ("heads", "inline"))
+    assert traffic == (5.0 * 1.01 + 1.0) * 1024.0 and got == r2
+    assert bench.counter_traffic("c.json", dict(tuning, chunk=4096), ("heads", "inline"))[0] is None
     assert bench.counter_traffic("c.json", tuning, ("direct", "inline"))[0] is None
     (tmp_path / "k.hip").write_bytes(b"kernel source, changed")
     assert bench.counter_traffic("c.json", tuning, ("heads", "inline"))[0] is None
@@ -59,14 +68,31 @@ def test_counter_record_checks(tmp_path, monkeypatch):
 
 
 def test_committed_counter_record_is_complete():
-    path = os.path.join(ROOT, "profiles", "mih_round_kernel_1e9x64_m2_k100_counters.json")
+    path = os.path.join(ROOT, "profiles", "mih_search_1e9x64_m2_k100_counters.json")
     rec = json.load(open(path))
-    for key in ("sources", "source_sha256_16", "tuning", "modes", "copy_calibration",
-                "fetch_kib_per_launch", "write_kib_per_launch", "commands"):
+    for key in ("sources", "source_sha256_16", "modes", "copy_calibration", "random_line_calibration",
+                "records", "commands"):
         assert key in rec, key
-    assert len(rec["fetch_kib_per_launch"]) == len(rec["write_kib_per_launch"]) == rec["launches"]
+    for r in rec["records"]:
+        assert len(r["fetch_kib_per_launch"]) == len(r["write_kib_per_launch"]) == r["launches"]
+        assert r["tuning"]
     for src in rec["sources"]:
         assert os.path.exists(os.path.join(ROOT, src)), src
+
+
+def test_search_roofline_counts_the_survey_bytes():
+    # 8 B per probe, 4 B id + bits/8 B code per candidate, bits/8 B per
+    # query and 8 B per output entry, over the rounds' event time
+    st = {"probes": 1000, "candidates": 300, "search_kernel_ms": 2.0, "search_launches": 4}
+    info = {"table_mode": "heads", "codes_mode": "inline"}
+    k_list = np.full(10, 7, dtype=np.uint32)
+    r = bench.search_roofline(st, info, 12345, 128, 4, 10, (7,), k_list, 2, {})
+    alg = 1000 * 8 + 300 * (4 + 16) + 10 * 16 + 70 * 8
+    assert r["alg_bytes_per_step"] == alg and r["alg_bytes_per_launch"] == alg // 4
+    assert r["achieved"] == round(alg / 2e-3 / 1e9, 1) and r["frac"] == round(alg / 2e-3 / 1e9 / 8000.0, 4)
+    assert r["traffic"] is None and r["random_lines"] is None
+    r2 = bench.search_roofline(st, dict(info, table_mode="sorted"), 12345, 128, 4, 10, (7,), k_list, 2, {})
+    assert r2["alg_bytes_per_step"] == alg + 1000 * 4
 
 
 def test_workload_overrides():
