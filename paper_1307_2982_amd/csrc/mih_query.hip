@@ -809,6 +809,7 @@ struct PartLds {
     uint32_t qtau[MIH_WAVE];         // bound of the query (refreshed after appends)
     uint64_t qg[MIH_WAVE][W];        // the query's words
     uint32_t queue[kQueue];          // occupied buckets: low key bits << 6 | wave query
+    uint16_t pend[2 * MIH_WAVE];     // group indices of queries with masks in the partition
 };
 
 // Verify candidate `code` (table position pos) of query k of the wave:
@@ -928,13 +929,14 @@ __device__ void part_tighten(const mih::MihArgs &A, PartLds<W, J> &S, uint64_t t
     wave_lds_sync();
 }
 
-// The queries i0 .. i0 + nq - 1 (at most 64) of the group at step t whose
-// active entries start at slot_start, against partition h of L key bits,
-// whose occupancy bits are in `occ` (bit v of the partition: word v / 32).
+// The queries S.pend[0 .. nq) (at most 64; indices in the group at step t
+// whose active entries start at slot_start) against partition h of L key
+// bits, whose occupancy bits are in `occ` (bit v of the partition: word
+// v / 32).
 template <int W, int TM, bool INLINE, int J>
 __device__ void part_queries(const mih::MihArgs &A, uint32_t t, uint32_t slot_start, uint32_t L, uint32_t h,
-                             uint32_t i0, uint32_t nq, const uint32_t *occ,
-                             const uint32_t (*binom)[MIH_BINOM_N], PartLds<W, J> &S, WaveStats &ws)
+                             uint32_t nq, const uint32_t *occ, const uint32_t (*binom)[MIH_BINOM_N],
+                             PartLds<W, J> &S, WaveStats &ws)
 {
     constexpr uint32_t D = kPartDepth, Q = PartLds<W, J>::kQueue;
     static_assert(Q >= MIH_WAVE * (kPartDepth + J), "queue holds a pass's rest and a block");
@@ -945,7 +947,7 @@ __device__ void part_queries(const mih::MihArgs &A, uint32_t t, uint32_t slot_st
 
     uint32_t M = 0;
     if (lane < nq) {
-        const uint32_t q = A.active[slot_start + i0 + lane];
+        const uint32_t q = A.active[slot_start + S.pend[lane]];
         uint64_t g[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) g[w] = A.qb.queries[(uint64_t)q * W + w];
@@ -1083,11 +1085,42 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_part_kernel(mih::MihArgs A)
                 staged_g = gl;
                 __syncthreads();
             }
+            // A query meets the partition through C(L, r' - w) masks, w the
+            // distance of its key's high bits to h: none when w > r' or
+            // r' - w > L (most queries at small r').  Each wave gathers the
+            // queries that meet it from its share of the item, and runs them
+            // 64 at a time, so that the set-up of a pass is paid for 64
+            // queries with masks.
             const uint32_t q0 = c * A.sweep_q;
             const uint32_t qn = gcount - q0 < A.sweep_q ? gcount - q0 : A.sweep_q;
+            const uint32_t rp = gt / A.m;
+            const TableDev &T = A.tables[gt - rp * A.m];
+            PartLds<W, J> &P = pq[wave];
+            uint32_t npend = 0;
             for (uint32_t s0 = wave * MIH_WAVE; s0 < qn; s0 += kWaves * MIH_WAVE) {
-                const uint32_t nq = qn - s0 < MIH_WAVE ? qn - s0 : MIH_WAVE;
-                part_queries<W, TM, INLINE, J>(A, gt, gslot, L, h, q0 + s0, nq, occ, binom, pq[wave], ws);
+                bool meets = false;
+                if (s0 + lane < qn) {
+                    const uint32_t q = A.active[gslot + q0 + s0 + lane];
+                    uint64_t g[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) g[w] = A.qb.queries[(uint64_t)q * W + w];
+                    const uint32_t wgt = __popc((table_key<W>(g, T) >> L) ^ h);
+                    meets = wgt <= rp && rp - wgt <= L;
+                }
+                const uint64_t bal = __ballot(meets);
+                if (meets) P.pend[npend + lanes_below(bal)] = (uint16_t)(q0 + s0 + lane);
+                npend += (uint32_t)__popcll(bal);
+                if (npend >= MIH_WAVE) {
+                    wave_lds_sync();
+                    part_queries<W, TM, INLINE, J>(A, gt, gslot, L, h, MIH_WAVE, occ, binom, P, ws);
+                    npend -= MIH_WAVE;
+                    if (lane < npend) P.pend[lane] = P.pend[MIH_WAVE + lane];
+                    wave_lds_sync();
+                }
+            }
+            if (npend) {
+                wave_lds_sync();
+                part_queries<W, TM, INLINE, J>(A, gt, gslot, L, h, npend, occ, binom, P, ws);
             }
         }
     }
