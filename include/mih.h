@@ -162,6 +162,11 @@ typedef struct mih_query_stats {
     double search_kernel_ms;   /* HIP-event time of the search kernel launches */
     uint32_t search_launches;  /* number of those launches                     */
     uint32_t pad;
+    double tail_ms;            /* summed over the device rounds: time from the
+                                  first to the last wave (round kernel) or
+                                  workgroup (sweep kernels) of a launch that
+                                  took work running out of it; the one-launch
+                                  path of small batches adds nothing        */
 } mih_query_stats;
 
 /* Per-call counters of the linear scan. */
@@ -388,9 +393,11 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning);
 /* Time mih_knn over a grid of tunings (probes_per_lane 4, 8, 16; chunk of
  * 2, 8, 32 or 128 times 64 * probes_per_lane; all workgroups that fit; with and
  * without the occupancy filter on DIRECT and HEADS tables; and, for
- * substrings of 20 bits or more, sweeps with sweep_shift 3: on tables with
- * an occupancy map 17 or 18 sweep bits and 4096 sweep queries, otherwise 18
- * or 20 sweep bits; the lookahead of the current tuning) on
+ * substrings of 20 bits or more, sweeps: on tables with an occupancy map
+ * the partition kernel with 4096 sweep queries at (probes_per_lane,
+ * sweep_bits, sweep_shift) = (4, 16, 3), (4, 17, 3), (4, 18, 3), (8, 17, 3)
+ * and (4, 17, 4), otherwise sweep_shift 3 with 18 or 20 sweep
+ * bits; the lookahead of the current tuning) on
  * the given sample of queries, time the three fastest twice more, then the
  * fastest with buffer_mult 4 and 16 twice each; keep the fastest in the
  * index and write it to *chosen (may be NULL).  Results do not depend on the tuning, so the

@@ -61,7 +61,8 @@ class QueryStats(ctypes.Structure):
                 ("appended", ctypes.c_uint64), ("steps", ctypes.c_uint64),
                 ("rounds", ctypes.c_uint32), ("reruns", ctypes.c_uint32),
                 ("elapsed_ms", ctypes.c_double), ("search_kernel_ms", ctypes.c_double),
-                ("search_launches", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+                ("search_launches", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("tail_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}

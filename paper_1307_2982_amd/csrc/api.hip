@@ -514,6 +514,7 @@ void copy_stats(const mih::EngineStats &es, clk::time_point t0, mih_query_stats 
     stats->reruns = es.reruns;
     stats->search_kernel_ms = es.search_kernel_ms;
     stats->search_launches = es.search_launches;
+    stats->tail_ms = es.tail_ms;
     stats->elapsed_ms = ms_since(t0);
 }
 
@@ -1012,7 +1013,7 @@ mih_status small_batch(mih_index *ix, const uint64_t *queries, uint32_t nq, cons
     S.nq = nq;
     // as many workgroups per query as the device holds at once (up to 8)
     const uint32_t resident =
-        num_cus() * (uint32_t)mih::mih_round_occupancy(A.W, A.tm, A.inline_codes, A.J, 3, 0);
+        num_cus() * (uint32_t)mih::mih_small_occupancy(A.W, A.tm, A.inline_codes, A.J);
     S.groups = std::min<uint32_t>(8, std::max<uint32_t>(1, resident / nq));
     S.row_off = (const uint64_t *)(d + o_ro);
     S.out_ids = out_ids;
@@ -1457,20 +1458,22 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
     for (uint32_t j = 0; j < idx->m; ++j) max_len = std::max(max_len, idx->len[j]);
     if (max_len >= mih::kSweepMinBits) {
         if (filters == 2) {
-            // tables with an occupancy map sweep in the partition kernel
-            for (uint32_t J : {4u, 8u})
-                for (uint32_t bits : {17u, 18u}) {
-                    const uint32_t sq = 4096;
-                    mih_tuning t = idx->tuning;
-                    t.probes_per_lane = J;
-                    t.chunk = 64 * J * 32;
-                    t.blocks_per_cu = 0;
-                    t.occupancy_filter = 1;
-                    t.sweep_shift = 3;
-                    t.sweep_bits = bits;
-                    t.sweep_queries = sq;
-                    grid.push_back(t);
-                }
+            // tables with an occupancy map sweep in the partition kernel:
+            // partition size, masks per lane of the round kernel, and which
+            // steps are swept (shift 4 also takes those of a quarter the size)
+            struct { uint32_t J, bits, shift; } part[] = {{4, 16, 3}, {4, 17, 3}, {4, 18, 3}, {8, 17, 3},
+                                                          {4, 17, 4}};
+            for (const auto &p : part) {
+                mih_tuning t = idx->tuning;
+                t.probes_per_lane = p.J;
+                t.chunk = 64 * p.J * 32;
+                t.blocks_per_cu = 0;
+                t.occupancy_filter = 1;
+                t.sweep_shift = p.shift;
+                t.sweep_bits = p.bits;
+                t.sweep_queries = 4096;
+                grid.push_back(t);
+            }
         } else {
             for (uint32_t J : {4u, 8u})
                 for (uint32_t bits : {18u, 20u}) {

@@ -89,6 +89,7 @@ struct EngineStats {
     uint32_t rounds = 0, reruns = 0;
     double search_kernel_ms = 0;
     uint32_t search_launches = 0;
+    double tail_ms = 0;   // rounds' tails: first to last wave of a search launch running out of work
 };
 
 // Runs queries over an index in rounds.  Per-query state lives in `slots`

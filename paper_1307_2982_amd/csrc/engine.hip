@@ -121,7 +121,7 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
                    o_nt = take(4ull * S_), o_new = take(4ull * S_), o_done = take(4ull * S_),
                    o_ovf = take(4ull * S_), o_btau = take(4ull * S_), o_bcap = take(4ull * S_),
                    o_grp = take(sizeof(Group) * (ix_->t_all + 1)), o_ctrl = take(sizeof(Control)),
-                   o_work = take(8 * (1 + kSweepXcds)), o_stats = take(8 * 4), o_adm = take(sizeof(AdmitRec) * S_),
+                   o_work = take(8 * (1 + kSweepXcds)), o_stats = take(8 * kStatSlots), o_adm = take(sizeof(AdmitRec) * S_),
                    o_tl = take(4ull * S_), o_tc = take(4ull * S_), o_mt = take(4ull * S_),
                    o_bg = take(4ull * S_), o_uq = take(4ull * S_), o_cur = take(4ull * S_);
     hipError_t e = hipMalloc(&dev_, used);
@@ -173,7 +173,7 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
     // zeroed control block, counters and statistics
     if ((e = fill_u32((uint32_t *)ctrl_, sizeof(Control) / 4, 0u, s_)) != hipSuccess) return e;
     if ((e = fill_u64((uint64_t *)work_, 1 + kSweepXcds, 0ull, s_)) != hipSuccess) return e;
-    if ((e = fill_u64((uint64_t *)stats_, 4, 0ull, s_)) != hipSuccess) return e;
+    if ((e = fill_u64((uint64_t *)stats_, kStatSlots, 0ull, s_)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
     free_slots_.resize(S_);
     for (uint32_t i = 0; i < S_; ++i) free_slots_[i] = S_ - 1 - i;
@@ -586,12 +586,12 @@ hipError_t Engine::complete(uint64_t ticket, Req &r, std::vector<uint64_t> &comp
 hipError_t Engine::reset_stats()
 {
     stats_host_ = EngineStats();
-    return fill_u64((uint64_t *)stats_, 4, 0ull, s_);
+    return fill_u64((uint64_t *)stats_, kStatSlots, 0ull, s_);
 }
 
 hipError_t Engine::read_stats(EngineStats &out)
 {
-    unsigned long long st[4] = {0, 0, 0, 0};
+    unsigned long long st[kStatSlots] = {};
     hipError_t e = sync_copy(st, stats_, sizeof(st), hipMemcpyDeviceToHost, s_);
     if (e != hipSuccess) return e;
     out = stats_host_;
@@ -599,6 +599,12 @@ hipError_t Engine::read_stats(EngineStats &out)
     out.candidates = st[1];
     out.steps = st[2];
     out.appended = st[3];
+    // the wall clock's rate (kHz) turns ticks into milliseconds
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+        out.tail_ms = (double)st[kStatTail] / khz;
+    (void)hipGetLastError();
     return hipSuccess;
 }
 

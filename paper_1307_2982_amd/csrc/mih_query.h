@@ -43,6 +43,11 @@ constexpr uint32_t kSweepQueries = 64;   // at most one per lane
 constexpr uint32_t kSweepMinBits = 20;
 constexpr uint32_t kSweepXcds = 8;
 constexpr uint32_t kSweepBatch = 4;   // consecutive sweep items claimed at once
+// Device statistics slots of the engine: 0 probes, 1 candidates, 2 steps,
+// 3 appended; 4-5 the round kernel's first and last wave end (the first as
+// a complement) in the current round, 6-7 the same for the sweep kernels,
+// 8 the sum of the rounds' tails in wall-clock ticks.
+constexpr uint32_t kStatRoundEnd = 4, kStatSweepEnd = 6, kStatTail = 8, kStatSlots = 9;
 static_assert(kSweepQueries <= MIH_WAVE, "one lane per query of a sweep item");
 // Partition kernel: the largest partition (key bits) whose occupancy bits
 // are staged in LDS (2^18 bits = 32 KiB).
@@ -138,6 +143,8 @@ struct SmallArgs {
 // A.qb describes the batch (queries [nq][W], k, cap, buf_off; tau = bits,
 // count = 0 and hist = 0 on entry); A.stats (4 counters) zero on entry.
 hipError_t mih_small(const MihArgs &A, const SmallArgs &S, hipStream_t s);
+// Workgroups per CU of the one-launch kernel.
+int mih_small_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J);
 // Whether the partition kernel exists for this layout.
 bool mih_part_kernel_ok(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J);
 bool mih_probes_per_lane_ok(uint32_t J);

@@ -27,357 +27,10 @@
 // (the wave alone owns the query, so it can test termination itself).
 // Between rounds a small kernel tests termination, moves unfinished queries
 // to their next non-empty step and regroups the active queries by step.
-#include "mih_common.h"
-#include "mih_query.h"
+#include "mih_step.h"
 #include "topk_dev.h"
 
 namespace {
-
-// J: masks per lane per iteration (a tuning knob; 64 J buckets are staged
-// per wave and iteration).
-constexpr uint32_t kWaves = MIH_BLOCK / MIH_WAVE;
-// Candidates per lane and pass of the candidate walk: more loads in flight
-// per wave, against the registers that keep them (64-bit codes: 2 keeps the
-// kernel at six waves per SIMD).
-template <int W>
-constexpr int walk_depth() { return W == 1 ? 2 : 4; }
-
-__device__ __forceinline__ uint32_t binom_calc(uint32_t n, uint32_t r)
-{
-    if (r > n) return 0;
-    uint64_t c = 1;
-    for (uint32_t i = 1; i <= r; ++i) c = c * (n - r + i) / i;
-    return (uint32_t)c;
-}
-
-// Colex unranking: the mask with `rho` set bits among s whose rank in
-// increasing numeric order is `rank` (combinatorial number system).
-__device__ __forceinline__ uint32_t unrank_mask(uint32_t rank, uint32_t rho, uint32_t s,
-                                                const uint32_t (*binom)[MIH_BINOM_N])
-{
-    uint32_t mask = 0;
-    int c = (int)s - 1;
-    for (int i = (int)rho; i >= 1; --i) {
-        while (c >= i && binom[c][i] > rank) --c;
-        rank -= binom[c][i];
-        mask |= 1u << c;
-        --c;
-    }
-    return mask;
-}
-
-// Next larger integer with the same number of set bits (Gosper).
-__device__ __forceinline__ uint32_t next_mask(uint32_t x)
-{
-    uint64_t v = x;
-    uint64_t c = v & (~v + 1);
-    uint64_t r = v + c;
-    return (uint32_t)((((r ^ v) >> 2) >> __builtin_ctzll(c)) | r);
-}
-
-template <int W>
-__device__ __forceinline__ uint64_t u64_uniform(uint64_t x)
-{
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-struct WaveStats {
-    uint64_t probes, candidates;
-};
-
-// Key of the code at table position pos (INLINE codes).  With contiguous
-// substrings only the one or two words that hold bits [start, start + len)
-// are read.
-template <int W>
-__device__ __forceinline__ uint32_t entry_key(const TableDev &T, uint64_t pos)
-{
-    const uint64_t *c = T.codes + pos * W;
-    if (T.permuted) {
-        uint64_t g[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) g[w] = c[w];
-        return table_key<W>(g, T);
-    }
-    const uint32_t w = T.start >> 6, o = T.start & 63;
-    uint64_t v = c[w] >> o;
-    if (o + T.len > 64) v |= c[w + 1] << (64 - o);
-    return (uint32_t)(v & ((T.len >= 32) ? 0xFFFFFFFFull : ((1ull << T.len) - 1)));
-}
-
-// First position in [p, n) whose substring value is at least `key`, given
-// that the values from p on are sorted and that one of them is at least key
-// or the range ends at n: doubling steps, then a binary search.
-template <int W>
-__device__ __forceinline__ uint32_t gallop_at_least(const TableDev &T, uint64_t n, uint64_t key,
-                                                    uint32_t p)
-{
-    uint64_t lo = p, step = 1;
-    while (lo + step <= n && entry_key<W>(T, lo + step - 1) < key) {
-        lo += step;
-        step <<= 1;
-    }
-    uint64_t hi = lo + step < n ? lo + step : n;   // the answer lies in [lo, hi]
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (entry_key<W>(T, mid) < key) lo = mid + 1; else hi = mid;
-    }
-    return (uint32_t)lo;
-}
-
-// GROUPED tables: the bucket `key`, known to be non-empty, inside the run of
-// codes sorted by substring value, starting the search at `p`, a position
-// no later than the bucket's first code.  Returns its first position and size.  The common case
-// (a few codes per group) is settled by one window of four entries read
-// together; longer runs fall back to doubling steps and a binary search.
-// Positions at or past n compare as larger than every value.
-template <int W>
-__device__ __forceinline__ void group_scan(const TableDev &T, uint64_t n, uint32_t key, uint32_t p,
-                                           uint32_t &lo, uint32_t &cnt)
-{
-    uint32_t lt = 0, eq = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint64_t pos = (uint64_t)p + i;
-        const uint64_t v = pos < n ? (uint64_t)entry_key<W>(T, pos) : (1ull << 32);
-        lt += v < key ? 1u : 0u;
-        eq += v == key ? 1u : 0u;
-    }
-    if (lt + eq < 4) {           // the window ends inside the bucket's successor
-        lo = p + lt;
-        cnt = eq;
-        return;
-    }
-    lo = lt < 4 ? p + lt : gallop_at_least<W>(T, n, key, p + 4);
-    if (lo >= n) {               // cannot happen for an occupied bucket; stay in bounds
-        cnt = 0;
-        return;
-    }
-    const uint32_t end = gallop_at_least<W>(T, n, (uint64_t)key + 1, lo + 1);
-    cnt = end - lo;
-}
-
-// The query's words (wave-uniform) and its key in table a.
-template <int W>
-__device__ __forceinline__ uint32_t query_key(const mih::MihArgs &A, uint32_t q, uint32_t a, uint64_t (&g)[W])
-{
-#pragma unroll
-    for (int w = 0; w < W; ++w) g[w] = u64_uniform<W>(A.qb.queries[(uint64_t)q * W + w]);
-    return table_key<W>(g, A.tables[a]);
-}
-
-// The buckets of a lane's J consecutive masks of rank r0 .. r0 + nmy - 1
-// (among the `nbits`-bit masks with `rho` set bits, xored into key_base):
-// their table positions [lo, lo + cnt) and, for HEADS tables, their first
-// codes.  Empty buckets (and masks past nmy) get cnt = 0.
-template <int W, int TM, int J>
-__device__ __forceinline__ void lookup_block(const mih::MihArgs &A, const TableDev &T, uint32_t key_base,
-                                             uint32_t nbits, uint32_t rho, uint32_t r0, uint32_t nmy,
-                                             const uint32_t (*binom)[MIH_BINOM_N], uint32_t (&lo)[J],
-                                             uint32_t (&cnt)[J], uint64_t (&head_code)[J])
-{
-    uint32_t keys[J];
-    uint32_t mask = nmy ? unrank_mask(r0, rho, nbits, binom) : 0u;
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        keys[j] = key_base ^ mask;
-        if ((uint32_t)j + 1 < nmy && rho > 0) mask = next_mask(mask);
-    }
-    // DIRECT tables with the occupancy filter: one bit per bucket says
-    // whether it holds codes; only occupied buckets read their offsets.
-    // GROUPED tables: the group record holds the same bits.
-    uint32_t occ_bits = ~0u;
-    uint32_t gbase[J];
-    if (TM == mih::TM_GROUPED) {
-        occ_bits = 0;
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            gbase[j] = 0;
-            if ((uint32_t)j < nmy) {
-                const uint64_t rec = T.grp[keys[j] >> 5];
-                const uint32_t bit = keys[j] & 31, occ = (uint32_t)rec;
-                if ((occ >> bit) & 1u) occ_bits |= 1u << j;
-                // every occupied bucket below this one in the group holds
-                // at least one code: the bucket starts no earlier than here
-                gbase[j] = (uint32_t)(rec >> 32) + __popc(occ & ((1u << bit) - 1u));
-            }
-        }
-    } else if ((TM == mih::TM_HEADS || TM == mih::TM_DIRECT) && A.occ_filter) {
-        occ_bits = 0;
-#pragma unroll
-        for (int j = 0; j < J; ++j)
-            if ((uint32_t)j < nmy && ((T.occ[keys[j] >> 5] >> (keys[j] & 31)) & 1u)) occ_bits |= 1u << j;
-    }
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        cnt[j] = 0;
-        lo[j] = 0;
-        if ((uint32_t)j < nmy && ((occ_bits >> j) & 1u)) {
-            const uint32_t key = keys[j];
-            if (TM == mih::TM_GROUPED) {
-                group_scan<W>(T, A.n, key, gbase[j], lo[j], cnt[j]);
-            } else if (TM == mih::TM_HEADS) {
-                const BucketHead h = T.head[key];   // one 16-byte entry, one line
-                lo[j] = h.start;
-                cnt[j] = h.count;
-                head_code[j] = h.code;
-            } else if (TM == mih::TM_DIRECT) {
-                const uint32_t b0 = T.off[key];
-                const uint32_t b1 = T.off[(uint64_t)key + 1];
-                lo[j] = b0;
-                cnt[j] = b1 - b0;
-            } else {
-                const uint32_t cell = key >> (T.len - T.dir_bits);
-                uint32_t x0 = T.dir[cell], x1 = T.dir[(uint64_t)cell + 1];
-                // first position with keys >= key, then first with keys > key
-                uint32_t l = x0, h = x1;
-                while (l < h) {
-                    uint32_t mid = l + ((h - l) >> 1);
-                    if (T.keys[mid] < key) l = mid + 1; else h = mid;
-                }
-                uint32_t e = l;
-                h = x1;
-                while (e < h) {
-                    uint32_t mid = e + ((h - e) >> 1);
-                    if (T.keys[mid] <= key) e = mid + 1; else h = mid;
-                }
-                lo[j] = l;
-                cnt[j] = e - l;
-            }
-        }
-    }
-}
-
-// Part of step t of query q: the buckets key_base ^ mask for the masks of
-// rank [rb, re) among the `nbits`-bit masks with `rho` set bits.  A whole
-// step is key_base = the query's key, nbits = s_a, rho = t / m; one key
-// partition of a step (the sweep kernel) fixes the high bits of the key and
-// enumerates the rest.
-template <int W, int TM, bool INLINE, int J>
-__device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t key_base,
-                             uint32_t nbits, uint32_t rho, uint32_t rb, uint32_t re,
-                             const uint32_t (*binom)[MIH_BINOM_N], uint32_t *stage_pos,
-                             uint32_t *stage_cum, uint64_t *stage_code, WaveStats &ws)
-{
-    const uint32_t lane = lane_id();
-    const uint32_t m = A.m;
-    const uint32_t rp = t / m, a = t - rp * m;
-    const TableDev T = A.tables[a];
-    // codes in table order: every table of an INLINE index, the leading
-    // tables of a MIXED one (whose kernels are the indirect ones)
-    const bool tinl = INLINE || T.codes != nullptr;
-    uint64_t g[W];
-    (void)query_key<W>(A, q, a, g);
-    uint32_t tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
-
-    for (uint32_t base = rb; base < re; base += MIH_WAVE * J) {
-        const uint32_t r0 = base + lane * J;
-        const uint32_t nmy = r0 < re ? (re - r0 < (uint32_t)J ? re - r0 : (uint32_t)J) : 0u;
-        uint32_t lo[J], cnt[J];
-        uint64_t head_code[J];   // HEADS: the first code of each bucket
-        lookup_block<W, TM, J>(A, T, key_base, nbits, rho, r0, nmy, binom, lo, cnt, head_code);
-        // stage the non-empty buckets of the wave with the running count of
-        // candidates before each, then walk the candidates 64 at a time
-        uint32_t ne = 0, tc = 0;
-#pragma unroll
-        for (int j = 0; j < J; ++j) { ne += cnt[j] ? 1u : 0u; tc += cnt[j]; }
-        const uint32_t ne_incl = wave_inclusive_sum(ne);
-        const uint32_t tc_incl = wave_inclusive_sum(tc);
-        const uint32_t NE = __shfl(ne_incl, MIH_WAVE - 1, MIH_WAVE);
-        const uint32_t TC = __shfl(tc_incl, MIH_WAVE - 1, MIH_WAVE);
-        uint32_t p = ne_incl - ne, c = tc_incl - tc;
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            if (cnt[j]) {
-                stage_pos[p] = lo[j];
-                stage_cum[p] = c;
-                if (TM == mih::TM_HEADS) stage_code[p] = head_code[j];
-                ++p;
-                c += cnt[j];
-            }
-        }
-        wave_lds_sync();
-        ws.probes += __shfl(wave_inclusive_sum(nmy), MIH_WAVE - 1, MIH_WAVE);
-        ws.candidates += TC;
-
-        constexpr int kWalk = walk_depth<W>();
-        // the candidates are walked kWalk x 64 at a time: lane l takes
-        // e0 + 64 u + l for u < kWalk, so every load instruction covers 64
-        // consecutive table positions, and the kWalk loads of a lane are in
-        // flight together
-        for (uint32_t e0 = 0; e0 < TC; e0 += MIH_WAVE * kWalk) {
-            const uint32_t nu = (TC - e0 + MIH_WAVE - 1) / MIH_WAVE;   // live slices (wave-uniform)
-            uint32_t bl[kWalk], pos[kWalk], id[kWalk];
-            bool live[kWalk];
-            uint64_t code[kWalk][W];
-            // staged bucket of each candidate: the last one whose running
-            // count is <= e (branch-free halving, the searches interleaved)
-#pragma unroll
-            for (int u = 0; u < kWalk; ++u) bl[u] = 0;
-            for (uint32_t len = NE; len > 1;) {
-                const uint32_t half = len >> 1;
-#pragma unroll
-                for (int u = 0; u < kWalk; ++u)
-                    if ((uint32_t)u < nu && stage_cum[bl[u] + half] <= e0 + u * MIH_WAVE + lane) bl[u] += half;
-                len -= half;
-            }
-#pragma unroll
-            for (int u = 0; u < kWalk; ++u) {
-                const uint32_t e = e0 + u * MIH_WAVE + lane;
-                live[u] = e < TC;
-                pos[u] = live[u] ? stage_pos[bl[u]] + (e - stage_cum[bl[u]]) : 0u;
-                id[u] = 0;
-                if (!tinl && live[u]) id[u] = T.ids[pos[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < kWalk; ++u) {
-                if (live[u]) {
-                    if (TM == mih::TM_HEADS && e0 + u * MIH_WAVE + lane == stage_cum[bl[u]]) {
-                        code[u][0] = stage_code[bl[u]];   // a bucket's first code came with its offsets
-                    } else if (tinl) {
-                        load_code<W>(T.codes + (uint64_t)pos[u] * W, code[u]);
-                    } else {
-                        load_code<W>(A.codes + (uint64_t)id[u] * W, code[u]);
-                    }
-                } else {
-#pragma unroll
-                    for (int w = 0; w < W; ++w) code[u][w] = g[w];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kWalk; ++u) {
-                if ((uint32_t)u >= nu) break;
-                const uint32_t d = hamming<W>(code[u], g);
-                // first encounter of the code (the de-duplication rule
-                // above); every candidate is tested when distinct codes are
-                // counted, else only those within tau
-                bool first = live[u] && (A.count_unique || d <= tau);
-                if (first) {
-                    uint64_t x[W];
-#pragma unroll
-                    for (int w = 0; w < W; ++w) x[w] = code[u][w] ^ g[w];
-                    for (uint32_t j = 0; j < m; ++j) {
-                        if (j == a) continue;
-                        const uint32_t dj = table_dist<W>(x, A.tables[j]);
-                        if (j < a ? dj <= rp : dj < rp) { first = false; break; }
-                    }
-                }
-                if (A.count_unique) {
-                    const uint64_t fb = __ballot(first);
-                    if (fb && lane == 0) atomicAdd(A.uniq + q, (uint32_t)__popcll(fb));
-                }
-                const bool keep = first && d <= tau;
-                if (keep && tinl) id[u] = T.ids[pos[u]];
-                append_candidates(A.qb, q, keep, d, id[u]);
-                if (__ballot(keep)) tau = tighten_tau(A.qb, q, tau);
-            }
-        }
-        wave_lds_sync();
-        const uint32_t g_tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
-        tau = g_tau < tau ? g_tau : tau;
-    }
-}
 
 template <int W, int TM, bool INLINE, int J>
 __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
@@ -395,11 +48,13 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
     const uint64_t total = A.ctrl->total_items;
     const uint32_t chunk = A.chunk;
     WaveStats ws = {0, 0};
+    bool worked = false;
     for (;;) {
         uint64_t item = 0;
         if (lane == 0) item = atomicAdd(A.work, 1ull);
         item = u64_uniform<1>(__shfl(item, 0, MIH_WAVE));
         if (item >= total) break;
+        worked = true;
         // group of the item: the last group whose first item is <= item
         uint32_t gl = 0, gh = n_groups;
         while (gh - gl > 1) {
@@ -457,6 +112,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
     if (lane == 0) {
         atomicAdd(&A.stats[0], (unsigned long long)ws.probes);
         atomicAdd(&A.stats[1], (unsigned long long)ws.candidates);
+        if (worked) record_end(A.stats + mih::kStatRoundEnd);
     }
 }
 
@@ -737,6 +393,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_sweep_kernel(mih::MihArgs A)
     const uint32_t n_groups = A.ctrl->n_groups;
     const uint32_t home = blockIdx.x % mih::kSweepXcds;
     WaveStats ws = {0, 0};
+    bool worked = false;
     for (uint32_t k = 0; k < mih::kSweepXcds; ++k) {
         const uint32_t x = (home + k) % mih::kSweepXcds;
         for (;;) {
@@ -746,6 +403,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_sweep_kernel(mih::MihArgs A)
             if (lane == 0) first = atomicAdd(A.work_sweep + x, (unsigned long long)mih::kSweepBatch);
             first = u64_uniform<1>(__shfl(first, 0, MIH_WAVE));
             if (first >= per_xcd) break;
+            worked = true;
             const uint64_t last = first + mih::kSweepBatch < per_xcd ? first + mih::kSweepBatch : per_xcd;
             for (uint64_t item = first; item < last; ++item) {
                 uint32_t gl = 0, gh = n_groups;
@@ -765,6 +423,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_sweep_kernel(mih::MihArgs A)
     if (lane == 0) {
         atomicAdd(&A.stats[0], (unsigned long long)ws.probes);
         atomicAdd(&A.stats[1], (unsigned long long)ws.candidates);
+        if (worked) record_end(A.stats + mih::kStatSweepEnd);
     }
 }
 
@@ -1055,6 +714,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_part_kernel(mih::MihArgs A)
     const uint32_t home = blockIdx.x % mih::kSweepXcds;
     uint32_t staged_h = 0xFFFFFFFFu, staged_g = 0xFFFFFFFFu;   // partition whose bits are in occ
     WaveStats ws = {0, 0};
+    bool worked = false;
     for (uint32_t k = 0; k < mih::kSweepXcds; ++k) {
         const uint32_t x = (home + k) % mih::kSweepXcds;
         for (;;) {
@@ -1063,6 +723,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_part_kernel(mih::MihArgs A)
             __syncthreads();
             const uint64_t item = s_item;
             if (item >= per_xcd) break;
+            worked = true;
             uint32_t gl = 0, gh = n_groups;
             while (gh - gl > 1) {
                 const uint32_t mid = (gl + gh) >> 1;
@@ -1127,189 +788,10 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_part_kernel(mih::MihArgs A)
     if (lane == 0) {
         atomicAdd(&A.stats[0], (unsigned long long)ws.probes);
         atomicAdd(&A.stats[1], (unsigned long long)ws.candidates);
+        if (worked && wave == 0) record_end(A.stats + mih::kStatSweepEnd);
     }
 }
 
-// ------------------------------------------------------------------------
-// One launch for a small batch: every query is taken by G workgroups, which
-// run all its steps (Algorithm 3) on the device with no host round trip and
-// no regroup between steps.  Steps go in windows: a window is one step, or
-// consecutive steps whose masks together fill at most one pass of the
-// query's waves.  Each workgroup takes its share of every window
-// (contiguous ranges of masks, one per wave), in step order; the workgroup
-// that finishes a window last (a counter per query and step) knows that
-// steps 0 .. tw are complete, tests termination (Proposition 2) and, if the
-// query is done, raises its stop flag.  The others do not wait for that test:
-// they go on with the next window and leave at the next window boundary
-// once the flag is up.  Steps they run ahead of the decision only add codes
-// farther than the stop step, which is the engine's lookahead and changes
-// no result.  A workgroup runs at most one window ahead of the completed
-// ones (a bounded wait at each window; past the bound it goes on).  The
-// workgroup that leaves last writes the top-k rows (or lists the query for
-// an exact re-run when its candidate buffer overflowed).  This is for batches too
-// small to fill the device with rounds, where the latency of the rounds,
-// not the number of probes, sets the time.
-template <int J>
-constexpr uint32_t small_waves() { return J >= 16 ? 4 : (J >= 8 ? 8 : 16); }   // LDS staging per wave
-// Most polls of a workgroup waiting for a step of its query to complete
-// (each a device-scope load and a short sleep: a few milliseconds at most).
-constexpr uint32_t kSmallPolls = 4096;
-
-template <int W, int TM, bool INLINE, int J>
-__global__ __launch_bounds__(small_waves<J>() * MIH_WAVE) void mih_small_kernel(
-    mih::MihArgs A, mih::SmallArgs S)
-{
-    constexpr uint32_t kW = small_waves<J>(), kThreads = kW * MIH_WAVE;
-    __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
-    // the staging of the search and the top-k of the last workgroup share LDS
-    struct Stage {
-        uint32_t pos[kW][MIH_WAVE * J];
-        uint32_t cum[kW][MIH_WAVE * J];
-        uint64_t code[kW][TM == mih::TM_HEADS ? MIH_WAVE * J : 1];
-    };
-    __shared__ union {
-        Stage st;
-        FinalizeLds fin;
-    } U;
-    uint32_t (&stage_pos)[kW][MIH_WAVE * J] = U.st.pos;
-    uint32_t (&stage_cum)[kW][MIH_WAVE * J] = U.st.cum;
-    auto &stage_code = U.st.code;
-    __shared__ uint32_t s_flag;
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += kThreads)
-        binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
-    __syncthreads();
-    WaveStats ws = {0, 0};
-    const uint32_t G = S.groups;
-    const uint32_t q = blockIdx.x / G, g = blockIdx.x - q * G;
-    if (q < S.nq && A.qb.k[q] != 0) {
-        uint32_t *step_cnt = S.step_cnt + (uint64_t)q * (A.t_all + 1);
-        // masks of one pass of all the query's waves: small steps run
-        // together in windows of at most one pass
-        const uint32_t pass = MIH_WAVE * J, cap = G * kW * pass;
-        auto masks_of = [&](uint32_t u) {
-            const uint32_t r = u / A.m;
-            return binom[A.tables[u - r * A.m].len][r];   // 0 when r' > s: the step covers radius u all the same
-        };
-        // expected candidates of a step (uniform codes: n / 2^s per bucket, at
-        // least one): a window keeps them to a quarter of the query's buffer,
-        // since the bound tau only falls once k codes have been found
-        auto cands_of = [&](uint32_t u) {
-            const uint32_t len = A.tables[u % A.m].len;
-            const uint64_t per = len >= 64 ? 0 : A.n >> len;
-            return (uint64_t)masks_of(u) * (per > 1 ? per : 1);
-        };
-        const uint64_t cand_cap = A.qb.cap[q] / 4;
-        constexpr uint32_t kNone = 0xFFFFFFFFu;
-        for (uint32_t t = 0, prev_tw = kNone, prev2_tw = kNone;;) {
-            // the window t .. tw: every step up to a pass of masks in all (at
-            // least step t), the same for every workgroup of the query
-            uint32_t tw = t, total = masks_of(t);
-            uint64_t cands = cands_of(t);
-            while (tw < A.t_all && total + masks_of(tw + 1) <= cap && cands + cands_of(tw + 1) <= cand_cap) {
-                ++tw;
-                total += masks_of(tw);
-                cands += cands_of(tw);
-            }
-            // A workgroup runs at most one window ahead of the completed
-            // ones: before a window it waits, a bounded number of polls, for
-            // the window before the previous one to complete (or the query to
-            // stop), and before a window larger than one pass of the query's
-            // waves for the previous one.  Without it, workgroups with no
-            // share of the small early windows would run far ahead, into
-            // steps past the stop, with the bound still loose.  Past the
-            // bound a workgroup goes on, which is only speculation.
-            const uint32_t need = total > cap ? prev_tw : prev2_tw;
-            if (need != kNone) {
-                if (tid == 0) {
-                    for (uint32_t i = 0; i < kSmallPolls; ++i) {
-                        if (load_relaxed(step_cnt + need) >= G || load_relaxed(S.stop + q) != kNone) break;
-                        __builtin_amdgcn_s_sleep(8);
-                    }
-                }
-                __syncthreads();
-            }
-            // the query's stop flag, seen at every window boundary
-            if (tid == 0) s_flag = load_relaxed(S.stop + q);
-            __syncthreads();
-            const bool stopped = s_flag != kNone;
-            __syncthreads();   // s_flag is rewritten below
-            if (stopped) break;
-            // contiguous ranges of whole passes over the window's masks, one per wave
-            const uint32_t per = ((total + G * kW - 1) / (G * kW) + pass - 1) / pass * pass;
-            const uint32_t rb = (g * kW + wave) * per;
-            const uint32_t re = rb + per < total ? rb + per : total;
-            uint32_t base = 0;
-            for (uint32_t u = t; u <= tw && base < re; ++u) {
-                const uint32_t M = masks_of(u);
-                const uint32_t lo = rb > base ? rb - base : 0u, hi = re - base < M ? re - base : M;
-                if (lo < hi) {
-                    const uint32_t rp = u / A.m, a = u - rp * A.m;
-                    uint64_t gq[W];
-                    process_step<W, TM, INLINE, J>(A, q, u, query_key<W>(A, q, a, gq), A.tables[a].len, rp, lo, hi,
-                                                   binom, stage_pos[wave], stage_cum[wave], stage_code[wave], ws);
-                }
-                base += M;
-            }
-            __syncthreads();   // this workgroup's share of the window is done
-            if (tid == 0) {
-                __threadfence();   // its candidates and counts before the step count
-                s_flag = atomicAdd(step_cnt + tw, 1u) + 1 == G ? 1u : 0u;
-                __threadfence();
-            }
-            __syncthreads();
-            const bool last = s_flag != 0;
-            __syncthreads();
-            if (last) {
-                // every workgroup has finished steps 0 .. tw: every code within
-                // distance tw has been found.  Algorithm 3 stops after step
-                // tau when tau <= tw (no earlier window reached tau), or
-                // after the last step
-                if (wave == 0) {
-                    uint32_t tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
-                    tau = tighten_tau(A.qb, q, tau);
-                    uint32_t stop = 0xFFFFFFFFu;
-                    if (tau <= tw) stop = tau > t ? tau : t;
-                    else if (tw >= A.t_all) stop = tw;
-                    if (lane == 0) s_flag = stop;
-                }
-                __syncthreads();
-                const uint32_t stop = s_flag;
-                if (stop != 0xFFFFFFFFu && tid == 0) atomicMin(S.stop + q, stop);
-                __syncthreads();
-                if (stop != 0xFFFFFFFFu) break;
-            } else if (tw >= A.t_all) {
-                break;   // the last step: its last finisher raises the flag
-            }
-            prev2_tw = prev_tw;
-            prev_tw = tw;
-            t = tw + 1;
-        }
-        // the workgroup that leaves last writes the rows
-        if (tid == 0) {
-            __threadfence();
-            s_flag = atomicAdd(S.exits + q, 1u) + 1 == G ? 1u : 0u;
-            __threadfence();
-        }
-        __syncthreads();
-        if (s_flag) {
-            const uint32_t cnt = load_relaxed(A.qb.count + q);
-            if (tid == 0) {
-                atomicAdd(&A.stats[2], (unsigned long long)load_relaxed(S.stop + q) + 1);   // steps
-                atomicAdd(&A.stats[3], (unsigned long long)cnt);                            // appended
-            }
-            if (cnt > A.qb.cap[q]) {
-                if (tid == 0) S.ovf_list[atomicAdd(S.ovf_count, 1u)] = q;
-            } else {
-                finalize_one(A.qb, q, S.out_ids + S.row_off[q], S.out_dists + S.row_off[q], U.fin);
-            }
-        }
-    }
-    if (lane == 0) {
-        atomicAdd(&A.stats[0], (unsigned long long)ws.probes);
-        atomicAdd(&A.stats[1], (unsigned long long)ws.candidates);
-    }
-}
 
 // After a round: termination test for the step each active query just
 // finished, and the next non-empty step for the others (a shell is empty
@@ -1318,6 +800,7 @@ __global__ __launch_bounds__(small_waves<J>() * MIH_WAVE) void mih_small_kernel(
 __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
 {
     const uint32_t i = blockIdx.x * MIH_BLOCK + threadIdx.x;
+    if (i == 0) fold_tails(A.stats);
     if (i >= A.ctrl->n_active) return;
     const uint32_t q = A.active[i];
     const uint32_t nb = A.qb.bits + 1;
@@ -1593,7 +1076,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_admit_kernel(mih::MihArgs A, co
 
 // Which kernel: the round kernel, the sweep kernel, or the partition
 // kernel (the sweep of tables with an occupancy map).
-enum { K_ROUND = 0, K_SWEEP = 1, K_PART = 2, K_SMALL = 3 };
+enum { K_ROUND = 0, K_SWEEP = 1, K_PART = 2 };
 
 // Kernel for (W, table mode, codes mode, J); J must be 4, 8 or 16.
 template <int W, int TM, bool INLINE, int J>
@@ -1604,7 +1087,6 @@ const void *kernel_of(int which)
             return reinterpret_cast<const void *>(&mih_part_kernel<W, TM, INLINE, J>);
         return nullptr;
     }
-    if (which == K_SMALL) return reinterpret_cast<const void *>(&mih_small_kernel<W, TM, INLINE, J>);
     return which == K_SWEEP ? reinterpret_cast<const void *>(&mih_sweep_kernel<W, TM, INLINE, J>)
                             : reinterpret_cast<const void *>(&mih_round_kernel<W, TM, INLINE, J>);
 }
@@ -1676,17 +1158,6 @@ hipError_t mih_sweep(const MihArgs &A, uint32_t grid, hipStream_t s)
     return hipLaunchKernel(k, dim3(grid), dim3(MIH_BLOCK), args, lds, s);
 }
 
-hipError_t mih_small(const MihArgs &A, const SmallArgs &S, hipStream_t s)
-{
-    const void *k = round_kernel(A.W, A.tm, A.inline_codes, A.J, K_SMALL);
-    if (!k) return hipErrorInvalidValue;
-    MihArgs a = A;
-    SmallArgs b = S;
-    void *args[] = {&a, &b};
-    const uint32_t block = (A.J >= 16 ? 4u : (A.J >= 8 ? 8u : 16u)) * MIH_WAVE;   // small_waves<J>() waves
-    return hipLaunchKernel(k, dim3(S.nq * S.groups), dim3(block), args, 0, s);
-}
-
 bool mih_part_kernel_ok(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J)
 {
     return round_kernel(W, tm, inline_codes, J, K_PART) != nullptr;
@@ -1697,9 +1168,8 @@ int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, 
 {
     const void *k = round_kernel(W, tm, inline_codes, J, which);
     const size_t lds = which == K_PART ? part_lds_bytes(part_bits) : 0;
-    const int block = which == K_SMALL ? (J >= 16 ? 4 : (J >= 8 ? 8 : 16)) * MIH_WAVE : MIH_BLOCK;
     int blocks = 0;
-    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, block, lds) != hipSuccess) {
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, MIH_BLOCK, lds) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
