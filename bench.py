@@ -590,11 +590,11 @@ def main():
         # rounds of a serving loop often hold few queries: smaller work items
         # spread them over more waves (the batch-tuned chunk is for full
         # batches); a work quantum keeps the rounds short, so that a request
-        # arriving meanwhile does not wait for whole large steps of others;
-        # steps are not swept (a sweep runs whole steps); requests go through
-        # the rounds (the one-launch path is for mih_knn calls)
-        serve_t = {"chunk": min(batch_t["chunk"], 8192), "round_masks": args.serve_quantum,
-                   "sweep_shift": 0}
+        # arriving meanwhile does not wait for whole large steps of others
+        # (steps larger than the quantum are not swept: a sweep runs a whole
+        # step); requests go through the rounds (the one-launch path is for
+        # mih_knn calls)
+        serve_t = {"chunk": min(batch_t["chunk"], 8192), "round_masks": args.serve_quantum}
         if args.serve_tuning:
             serve_t = {f: int(v) for f, v in (kv.split("=") for kv in args.serve_tuning.split(","))}
         idx.set_tuning(**serve_t)

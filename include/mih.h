@@ -371,8 +371,16 @@ typedef struct mih_tuning {
                                   loop stay short and requests that arrive
                                   meanwhile do not wait for a whole large
                                   step of the others.  Rounded up to whole
-                                  work items (chunk); steps are then never
-                                  swept */
+                                  work items (chunk); only steps within one
+                                  quantum are then swept */
+    uint32_t spill_codes;      /* 0 (off) or 256..: a bucket holding more
+                                  codes than this, met by the round kernel,
+                                  is cut into pieces of 1024 codes that any
+                                  wave of the kernel may walk (waves out of
+                                  work take them first), so that huge buckets
+                                  of clustered codes do not leave one wave
+                                  searching alone at the end of a round.
+                                  Exact searches only */
 } mih_tuning;
 
 #define MIH_LOOKAHEAD_MAX 32u
@@ -381,7 +389,8 @@ typedef struct mih_tuning {
 /* Current tuning of an index (defaults after mih_build: 4, 8192, 0, the
  * occupancy filter on for DIRECT and HEADS tables of substrings of 26 bits
  * or more, sweep off, 18 sweep bits, lookahead MIH_LOOKAHEAD_DEFAULT, 256
- * sweep queries, buffer_mult 8, small_batch 512, round_masks 0; HEADS tables
+ * sweep queries, buffer_mult 8, small_batch 512, round_masks 0,
+ * spill_codes 0; HEADS tables
  * of substrings of 26 bits or more start at 4 probes per lane, chunk 8192
  * and sweeps with sweep_shift 3, 17 sweep bits and 4096 sweep queries). */
 mih_status mih_get_tuning(const mih_index *idx, mih_tuning *tuning);
@@ -399,7 +408,9 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning);
  * and (4, 17, 4), otherwise sweep_shift 3 with 18 or 20 sweep
  * bits; the lookahead of the current tuning) on
  * the given sample of queries, time the three fastest twice more, then the
- * fastest with buffer_mult 4 and 16 twice each; keep the fastest in the
+ * fastest with buffer_mult 4 and 16 twice each, then the fastest with
+ * spill_codes 4096 and 32768 twice each (these last two changes must win
+ * by 3%); keep the fastest in the
  * index and write it to *chosen (may be NULL).  Results do not depend on the tuning, so the
  * sample only has to look like the real queries (how far rounds run ahead
  * depends on the batch size: a sample as large as the real batches tunes

@@ -84,7 +84,7 @@ class Tuning(ctypes.Structure):
                 ("sweep_shift", ctypes.c_uint32), ("sweep_bits", ctypes.c_uint32),
                 ("lookahead", ctypes.c_uint32), ("sweep_queries", ctypes.c_uint32),
                 ("buffer_mult", ctypes.c_uint32), ("small_batch", ctypes.c_uint32),
-                ("round_masks", ctypes.c_uint32)]
+                ("round_masks", ctypes.c_uint32), ("spill_codes", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -285,8 +285,8 @@ class Index:
     def set_tuning(self, **fields):
         """Launch tuning (speed only): any fields of mih_tuning (probes_per_lane,
         chunk, blocks_per_cu, occupancy_filter, sweep_shift, sweep_bits,
-        lookahead, sweep_queries, buffer_mult, small_batch, round_masks); the
-        others keep their value."""
+        lookahead, sweep_queries, buffer_mult, small_batch, round_masks,
+        spill_codes); the others keep their value."""
         cur = self.get_tuning()
         for f, v in fields.items():
             if f not in cur:

@@ -966,6 +966,41 @@ mih_status small_batch(mih_index *ix, const uint64_t *queries, uint32_t nq, cons
                    o_cap = field(4ull * nq), o_oc = field(8), o_tau = field(4ull * nq + 64),
                    o_cnt = field(4ull * nq), o_hist = field(4ull * nq * nb), o_stop = field(4ull * nq),
                    o_exit = field(4ull * nq), o_sc = field(4ull * nq * nsteps);
+    // workgroups per query: the device's resident workgroups shared in
+    // proportion to each query's expected probes (uniform-code model at its
+    // k), at least 1 and at most 8 each
+    if (ix->small_resident_J != ix->tuning.probes_per_lane) {
+        mih::MihArgs L = {};
+        mih::index_args(ix, L);
+        ix->small_resident = num_cus() * (uint32_t)mih::mih_small_occupancy(L.W, L.tm, L.inline_codes, L.J);
+        ix->small_resident_J = ix->tuning.probes_per_lane;
+    }
+    const uint32_t resident = ix->small_resident;
+    std::vector<uint64_t> work(nq);
+    double sum = 0;
+    {
+        std::vector<std::pair<uint32_t, uint64_t>> seen;   // the model per distinct k
+        for (uint32_t i = 0; i < nq; ++i) {
+            uint64_t w = 0;
+            if (kv[i]) {
+                auto it = std::find_if(seen.begin(), seen.end(), [&](const auto &p) { return p.first == kv[i]; });
+                if (it == seen.end()) {
+                    seen.emplace_back(kv[i], model_probes(ix, kv[i]));
+                    it = seen.end() - 1;
+                }
+                w = it->second;
+            }
+            work[i] = w;
+            sum += (double)w;
+        }
+    }
+    std::vector<uint32_t> first(nq + 1, 0);
+    for (uint32_t i = 0; i < nq; ++i) {
+        const double share = sum > 0 ? (double)resident * (double)work[i] / sum : 1.0;
+        first[i + 1] = first[i] + std::min<uint32_t>(8, std::max<uint32_t>(1, (uint32_t)share));
+    }
+    const uint32_t blocks = first[nq];
+    const uint64_t o_first = field(4ull * (nq + 1)), o_qof = field(4ull * blocks);
     // then, not uploaded: the overflow list and the candidate buffers
     const uint64_t o_ol = align_up(up, 256), o_buf = align_up(o_ol + 4ull * nq, 256);
     const uint64_t dev_bytes = o_buf + 8 * std::max<uint64_t>(entries, 1);
@@ -990,6 +1025,9 @@ mih_status small_batch(mih_index *ix, const uint64_t *queries, uint32_t nq, cons
     std::memcpy(h + o_ro, row_off.data(), 8ull * nq);
     std::memcpy(h + o_k, kv.data(), 4ull * nq);
     std::memcpy(h + o_cap, cap.data(), 4ull * nq);
+    std::memcpy(h + o_first, first.data(), 4ull * (nq + 1));
+    for (uint32_t i = 0; i < nq; ++i)
+        for (uint32_t b = first[i]; b < first[i + 1]; ++b) reinterpret_cast<uint32_t *>(h + o_qof)[b] = i;
     for (uint32_t i = 0; i < nq; ++i) {
         reinterpret_cast<uint32_t *>(h + o_tau)[i] = ix->bits;
         reinterpret_cast<uint32_t *>(h + o_stop)[i] = 0xFFFFFFFFu;
@@ -1011,10 +1049,9 @@ mih_status small_batch(mih_index *ix, const uint64_t *queries, uint32_t nq, cons
     A.stats = (unsigned long long *)(d + o_st);
     mih::SmallArgs S = {};
     S.nq = nq;
-    // as many workgroups per query as the device holds at once (up to 8)
-    const uint32_t resident =
-        num_cus() * (uint32_t)mih::mih_small_occupancy(A.W, A.tm, A.inline_codes, A.J);
-    S.groups = std::min<uint32_t>(8, std::max<uint32_t>(1, resident / nq));
+    S.blocks = blocks;
+    S.first = (const uint32_t *)(d + o_first);
+    S.query_of = (const uint32_t *)(d + o_qof);
     S.row_off = (const uint64_t *)(d + o_ro);
     S.out_ids = out_ids;
     S.out_dists = out_dists;
@@ -1290,6 +1327,7 @@ mih_status mih_set_tuning(mih_index *idx, const mih_tuning *tuning)
     if (tuning->buffer_mult < 1 || tuning->buffer_mult > 64) return MIH_ERR_INVALID;
     if (tuning->small_batch > 65536) return MIH_ERR_INVALID;
     if (tuning->round_masks > (1u << 30)) return MIH_ERR_INVALID;
+    if (tuning->spill_codes != 0 && tuning->spill_codes < 256) return MIH_ERR_INVALID;
     std::lock_guard<std::mutex> lock(idx->mu);
     idx->tuning = *tuning;
     idx->tuning_version++;
@@ -1520,8 +1558,26 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
         ms.resize(grid.size(), 1e300);
         for (int rep = 0; rep < 2 && st == MIH_OK; ++rep)
             for (size_t i = base; i < grid.size() && st == MIH_OK; ++i) time_one(i);
+        // a change of capacity must win by 3%: a sample's timings vary by
+        // about that much, and a smaller buffer risks re-runs on other batches
         for (size_t i = base; i < grid.size(); ++i)
-            if (ms[i] < best_ms) { best_ms = ms[i]; best = grid[i]; }
+            if (ms[i] < best_ms * 0.97) { best_ms = ms[i]; best = grid[i]; }
+    }
+    // huge buckets shared out in pieces (clustered codes): with the best
+    // launch so far, two sizes from which a bucket is cut (it must win by 3%:
+    // its kernel variant holds more registers)
+    if (st == MIH_OK && best.spill_codes == 0) {
+        const size_t base = grid.size();
+        for (uint32_t sc : {4096u, 32768u}) {
+            mih_tuning t = best;
+            t.spill_codes = sc;
+            grid.push_back(t);
+        }
+        ms.resize(grid.size(), 1e300);
+        for (int rep = 0; rep < 2 && st == MIH_OK; ++rep)
+            for (size_t i = base; i < grid.size() && st == MIH_OK; ++i) time_one(i);
+        for (size_t i = base; i < grid.size(); ++i)
+            if (ms[i] < best_ms * 0.97) { best_ms = ms[i]; best = grid[i]; }
     }
     mih_status st2 = mih_set_tuning(idx, st == MIH_OK ? &best : &start);
     out.release();

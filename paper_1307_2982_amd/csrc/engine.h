@@ -67,7 +67,7 @@ struct mih_index {
     std::vector<void *> allocs;
     uint64_t device_bytes = 0;
     double build_ms = 0;
-    mih_tuning tuning = {4, 8192, 0, 0, 0, 18, MIH_LOOKAHEAD_DEFAULT, 256, 8, 512, 0};
+    mih_tuning tuning = {4, 8192, 0, 0, 0, 18, MIH_LOOKAHEAD_DEFAULT, 256, 8, 512, 0, 0};
     uint32_t tuning_version = 0;
     std::mutex mu;
     std::unique_ptr<mih::Engine> batch_engine;   // reused by mih_knn calls
@@ -77,6 +77,7 @@ struct mih_index {
     uint64_t small_dev_bytes = 0;
     void *small_host = nullptr;
     uint64_t small_host_bytes = 0;
+    uint32_t small_resident = 0, small_resident_J = 0;   // workgroups the one-launch kernel keeps resident
 
     hipError_t alloc(void **p, uint64_t bytes);
     ~mih_index();
@@ -184,6 +185,9 @@ private:
     Group *groups_ = nullptr;
     Control *ctrl_ = nullptr;
     unsigned long long *work_ = nullptr, *stats_ = nullptr;
+    SpillRec *spill_ = nullptr;
+    uint32_t *spill_flag_ = nullptr;
+    unsigned long long *spill_cnt_ = nullptr;
     AdmitRec *admit_dev_ = nullptr;
     Control *ctrl_host_ = nullptr;   // pinned
     uint32_t *done_host_ = nullptr;  // pinned [slots]: the last round's done list

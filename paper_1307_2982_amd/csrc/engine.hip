@@ -121,7 +121,7 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
                    o_nt = take(4ull * S_), o_new = take(4ull * S_), o_done = take(4ull * S_),
                    o_ovf = take(4ull * S_), o_btau = take(4ull * S_), o_bcap = take(4ull * S_),
                    o_grp = take(sizeof(Group) * (ix_->t_all + 1)), o_ctrl = take(sizeof(Control)),
-                   o_work = take(8 * (1 + kSweepXcds)), o_stats = take(8 * kStatSlots), o_adm = take(sizeof(AdmitRec) * S_),
+                   o_work = take(8 * (1 + kSweepXcds)), o_scnt = take(4096), o_spill = take(sizeof(SpillRec) * kSpillCap), o_sflag = take(4ull * kSpillCap), o_stats = take(8 * kStatSlots), o_adm = take(sizeof(AdmitRec) * S_),
                    o_tl = take(4ull * S_), o_tc = take(4ull * S_), o_mt = take(4ull * S_),
                    o_bg = take(4ull * S_), o_uq = take(4ull * S_), o_cur = take(4ull * S_);
     hipError_t e = hipMalloc(&dev_, used);
@@ -150,6 +150,9 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
     groups_ = (Group *)(b + o_grp);
     ctrl_ = (Control *)(b + o_ctrl);
     work_ = (unsigned long long *)(b + o_work);
+    spill_ = (SpillRec *)(b + o_spill);
+    spill_flag_ = (uint32_t *)(b + o_sflag);
+    spill_cnt_ = (unsigned long long *)(b + o_scnt);
     stats_ = (unsigned long long *)(b + o_stats);
     admit_dev_ = (AdmitRec *)(b + o_adm);
     tmp_list_ = (uint32_t *)(b + o_tl);
@@ -173,7 +176,9 @@ hipError_t Engine::init(uint32_t slots, uint64_t pool_entries, bool use_graph)
     // zeroed control block, counters and statistics
     if ((e = fill_u32((uint32_t *)ctrl_, sizeof(Control) / 4, 0u, s_)) != hipSuccess) return e;
     if ((e = fill_u64((uint64_t *)work_, 1 + kSweepXcds, 0ull, s_)) != hipSuccess) return e;
+    if ((e = fill_u64((uint64_t *)spill_cnt_, 512, 0ull, s_)) != hipSuccess) return e;
     if ((e = fill_u64((uint64_t *)stats_, kStatSlots, 0ull, s_)) != hipSuccess) return e;
+    if ((e = fill_u32(spill_flag_, kSpillCap, 0u, s_)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
     free_slots_.resize(S_);
     for (uint32_t i = 0; i < S_; ++i) free_slots_[i] = S_ - 1 - i;
@@ -206,13 +211,14 @@ void Engine::fill_args(MihArgs &A) const
 {
     index_args(ix_, A);
     // the work quantum in whole work items; steps cut into portions are
-    // never swept (a sweep runs a whole step)
+    // never swept (a sweep runs a whole step): the regroup kernel sweeps
+    // only steps within one quantum
     A.quantum_items = ix_->tuning.round_masks
                           ? std::max<uint32_t>(1u, (ix_->tuning.round_masks + A.chunk - 1) / A.chunk)
                           : 0u;
     A.cursor = cursor_;
     // distinct codes are counted in whole-step probing only
-    A.sweep_shift = (count_unique_ || A.quantum_items) ? 0u : ix_->tuning.sweep_shift;
+    A.sweep_shift = count_unique_ ? 0u : ix_->tuning.sweep_shift;
     A.count_unique = count_unique_ ? 1u : 0u;
     A.max_t = max_t_;
     A.budget = budget_;
@@ -243,6 +249,14 @@ void Engine::fill_args(MihArgs &A) const
     A.work = work_;
     A.work_sweep = work_ + 1;
     A.stats = stats_;
+    // huge buckets are shared out in pieces among the waves of the round
+    // kernel (not where distinct codes are counted: a piece's walk does not)
+    A.spill = spill_;
+    A.spill_flag = spill_flag_;
+    A.spill_tail = spill_cnt_;          // its own 128-byte line
+    A.spill_next = spill_cnt_ + 16;     // and this one
+    A.spill_cap = kSpillCap;
+    A.spill_min = count_unique_ ? 0u : ix_->tuning.spill_codes;
 }
 
 uint64_t Engine::submit(const uint64_t *queries, uint32_t nq, const uint32_t *k,
@@ -391,7 +405,7 @@ hipError_t Engine::capture_graph()
     if (graph_) { (void)hipGraphDestroy(graph_); graph_ = nullptr; }
     MihArgs A;
     fill_args(A);
-    uint32_t per_cu = (uint32_t)mih_round_occupancy(A.W, A.tm, A.inline_codes, A.J, 0, 0);
+    uint32_t per_cu = (uint32_t)mih_round_occupancy(A.W, A.tm, A.inline_codes, A.J, A.spill_min ? 3 : 0, 0);
     if (ix_->tuning.blocks_per_cu && ix_->tuning.blocks_per_cu < per_cu) per_cu = ix_->tuning.blocks_per_cu;
     round_grid_ = cu_count() * per_cu;
     uint32_t per_cu_sweep =

@@ -60,6 +60,11 @@ __device__ __forceinline__ uint32_t load_relaxed(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // Inclusive prefix sum over the 64 lanes of a wave.

@@ -62,9 +62,17 @@ struct Control {
     uint32_t n_new;       // queries admitted since the last regroup
     uint32_t n_done;      // queries finished by the last advance
     uint32_t n_ovf;       // queries finished with an overflowed buffer
-    uint32_t pad;
+    uint32_t seq;         // rounds run (the spill flags of this round hold 2 seq, 2 seq + 1)
     uint64_t sweep_items; // items of the sweep kernel per XCD in the current round
 };
+
+// A piece of a huge bucket offered to every wave of the round kernel:
+// table positions [pos, pos + len) of step t's table, for query slot.
+struct SpillRec {
+    uint32_t slot, t, pos, len;
+};
+constexpr uint32_t kSpillPiece = 1024;      // codes per piece
+constexpr uint32_t kSpillCap = 1u << 20;    // pieces one round can offer
 
 // One admitted query: its slot and the state it starts from.
 struct AdmitRec {
@@ -118,20 +126,34 @@ struct MihArgs {
     Control *ctrl;
     unsigned long long *work; // work-item counter
     unsigned long long *work_sweep; // [kSweepXcds] work-item counters of the sweep kernel
-    unsigned long long *stats;// [2] probes, candidates
+    unsigned long long *stats;// [kStatSlots] counters (probes, candidates, ...)
+    // Buckets of more than spill_min codes (0: never) are cut into pieces of
+    // kSpillPiece codes that any wave of the round kernel may take: piece i
+    // is offered once spill_flag[i] = 2 seq (the round's sequence number)
+    // and taken by whoever turns it into 2 seq + 1.
+    SpillRec *spill;                  // [spill_cap]
+    uint32_t *spill_flag;             // [spill_cap]
+    unsigned long long *spill_tail;   // pieces reserved this round
+    unsigned long long *spill_next;   // next piece offered to helping waves
+    uint32_t spill_cap;
+    uint32_t spill_min;
 };
 
 hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s);
 // The swept groups of the round (returns at once when there are none).
 hipError_t mih_sweep(const MihArgs &A, uint32_t grid, hipStream_t s);
-// Workgroups per CU of a kernel (which: 0 round, 1 sweep, 2 partition).
+// Workgroups per CU of a kernel (which: 0 round, 1 sweep, 2 partition,
+// 3 round with huge buckets shared in pieces).
 int mih_round_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J, int which,
                         uint32_t part_bits);
 // One launch for a small batch of exact queries: `groups` workgroups per
 // query run every step and the last to leave writes the top-k rows.
 struct SmallArgs {
     uint32_t nq;
-    uint32_t groups;          // workgroups per query
+    uint32_t blocks;          // workgroups of the launch
+    const uint32_t *first;    // [nq + 1] first workgroup of each query (query q has
+                              // first[q + 1] - first[q] >= 1 workgroups)
+    const uint32_t *query_of; // [blocks] the query of each workgroup
     const uint64_t *row_off;  // [nq] output row of each query
     uint32_t *out_ids, *out_dists;
     uint32_t *stop;           // [nq] ~0, then the step after which the query stopped

@@ -32,13 +32,14 @@
 
 namespace {
 
-template <int W, int TM, bool INLINE, int J>
+template <int W, int TM, bool INLINE, int J, bool SPILL>
 __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
 {
     __shared__ uint32_t binom[MIH_BINOM_N][MIH_BINOM_N];
     __shared__ uint32_t stage_pos[kWaves][MIH_WAVE * J];
     __shared__ uint32_t stage_cum[kWaves][MIH_WAVE * J];
     __shared__ uint64_t stage_code[kWaves][TM == mih::TM_HEADS ? MIH_WAVE * J : 1];
+    __shared__ uint2 big[kWaves][SPILL ? kSpillList : 1];   // huge buckets of the wave's last step
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (uint32_t i = tid; i < MIH_BINOM_N * MIH_BINOM_N; i += MIH_BLOCK)
         binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
@@ -47,9 +48,12 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
     const uint32_t n_groups = A.ctrl->n_groups;
     const uint64_t total = A.ctrl->total_items;
     const uint32_t chunk = A.chunk;
+    const uint32_t seq = A.ctrl->seq;
     WaveStats ws = {0, 0};
     bool worked = false;
     for (;;) {
+        // pieces of huge buckets that other waves offer come first
+        if (SPILL) help_spilled<W, INLINE>(A, seq, ws);
         uint64_t item = 0;
         if (lane == 0) item = atomicAdd(A.work, 1ull);
         item = u64_uniform<1>(__shfl(item, 0, MIH_WAVE));
@@ -82,8 +86,14 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
         const uint32_t re = rb + chunk < M ? rb + chunk : M;
         uint64_t gq[W];
         const uint32_t a0 = t - rp * A.m;
-        process_step<W, TM, INLINE, J>(A, q, t, query_key<W>(A, q, a0, gq), A.tables[a0].len, rp, rb, re,
-                                       binom, stage_pos[wave], stage_cum[wave], stage_code[wave], ws);
+        const uint32_t nbig = process_step<W, TM, INLINE, J, SPILL>(
+            A, q, t, query_key<W>(A, q, a0, gq), A.tables[a0].len, rp, rb, re, binom, stage_pos[wave],
+            stage_cum[wave], stage_code[wave], ws, big[wave]);
+        // huge buckets: offered in pieces to the other waves, this wave
+        // taking those they have not
+        if (SPILL)
+            for (uint32_t i = 0; i < nbig; ++i)
+                spill_bucket<W, INLINE>(A, seq, q, t, big[wave][i].x, big[wave][i].y, ws);
         if (ipq != 1 || steps != 1 || !G->final) continue;
         // the whole step (or its last portion) belonged to this wave: keep
         // going while steps are small
@@ -96,11 +106,15 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
             const uint32_t rpn = tn / A.m;
             const uint32_t Mn = binom[A.tables[tn - rpn * A.m].len][rpn];
             if (Mn > chunk) break;
+            if (SPILL) help_spilled<W, INLINE>(A, seq, ws);   // others' huge buckets first
             if (Mn) {
                 const uint32_t an = tn - rpn * A.m;
-                process_step<W, TM, INLINE, J>(A, q, tn, query_key<W>(A, q, an, gq), A.tables[an].len, rpn,
-                                               0, Mn, binom, stage_pos[wave], stage_cum[wave],
-                                               stage_code[wave], ws);
+                const uint32_t nb = process_step<W, TM, INLINE, J, SPILL>(
+                    A, q, tn, query_key<W>(A, q, an, gq), A.tables[an].len, rpn, 0, Mn, binom, stage_pos[wave],
+                    stage_cum[wave], stage_code[wave], ws, big[wave]);
+                if (SPILL)
+                    for (uint32_t i = 0; i < nb; ++i)
+                        spill_bucket<W, INLINE>(A, seq, q, tn, big[wave][i].x, big[wave][i].y, ws);
             }
             t = tn;
             if (lane == 0) {
@@ -109,10 +123,14 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
             }
         }
     }
+    if (worked && lane == 0) record_end(A.stats + mih::kStatRoundEnd);   // out of work items
+    // out of work items: take what is offered now, then leave (waiting for
+    // more would put device-scope polls of many waves on the path of the
+    // atomics of the waves still searching)
+    if (SPILL) help_spilled<W, INLINE>(A, seq, ws);
     if (lane == 0) {
         atomicAdd(&A.stats[0], (unsigned long long)ws.probes);
         atomicAdd(&A.stats[1], (unsigned long long)ws.candidates);
-        if (worked) record_end(A.stats + mih::kStatRoundEnd);
     }
 }
 
@@ -933,8 +951,9 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
             // many probes per bucket line: run the step partition by
             // partition (sweep kernel; no items of the round kernel); the
             // quantum cuts steps into portions of Qi items, the final one
-            // holding what is left after the whole portions
-            const bool sweep = A.sweep_shift != 0 && s >= mih::kSweepMinBits &&
+            // holding what is left after the whole portions, and only steps
+            // within one quantum are swept (a sweep runs a whole step)
+            const bool sweep = A.sweep_shift != 0 && s >= mih::kSweepMinBits && (Qi == 0 || it <= Qi) &&
                                (uint64_t)c * M >= ((1ull << s) >> A.sweep_shift);
             uint32_t ipq = it;
             if (Qi) ipq = fin ? it - (it ? (it - 1) / Qi * Qi : 0u) : Qi;
@@ -1042,6 +1061,9 @@ __global__ __launch_bounds__(1024) void mih_regroup_kernel(mih::MihArgs A)
         ctrl->n_ovf = 0;
         *A.work = 0;
         for (uint32_t x = 0; x < mih::kSweepXcds; ++x) A.work_sweep[x] = 0;
+        *A.spill_tail = 0;
+        *A.spill_next = 0;
+        A.ctrl->seq += 1;   // the pieces offered in earlier rounds no longer count
     }
 }
 
@@ -1076,7 +1098,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_admit_kernel(mih::MihArgs A, co
 
 // Which kernel: the round kernel, the sweep kernel, or the partition
 // kernel (the sweep of tables with an occupancy map).
-enum { K_ROUND = 0, K_SWEEP = 1, K_PART = 2 };
+enum { K_ROUND = 0, K_SWEEP = 1, K_PART = 2, K_ROUND_SPILL = 3 };
 
 // Kernel for (W, table mode, codes mode, J); J must be 4, 8 or 16.
 template <int W, int TM, bool INLINE, int J>
@@ -1088,7 +1110,8 @@ const void *kernel_of(int which)
         return nullptr;
     }
     return which == K_SWEEP ? reinterpret_cast<const void *>(&mih_sweep_kernel<W, TM, INLINE, J>)
-                            : reinterpret_cast<const void *>(&mih_round_kernel<W, TM, INLINE, J>);
+           : which == K_ROUND_SPILL ? reinterpret_cast<const void *>(&mih_round_kernel<W, TM, INLINE, J, true>)
+                                    : reinterpret_cast<const void *>(&mih_round_kernel<W, TM, INLINE, J, false>);
 }
 
 template <int W, int TM, bool INLINE>
@@ -1143,7 +1166,7 @@ bool mih_probes_per_lane_ok(uint32_t J) { return J == 4 || J == 8 || J == 16; }
 
 hipError_t mih_round(const MihArgs &A, uint32_t grid, hipStream_t s)
 {
-    const void *k = round_kernel(A.W, A.tm, A.inline_codes, A.J, K_ROUND);
+    const void *k = round_kernel(A.W, A.tm, A.inline_codes, A.J, A.spill_min ? K_ROUND_SPILL : K_ROUND);
     if (!k) return hipErrorInvalidValue;
     void *args[] = {const_cast<MihArgs *>(&A)};
     return hipLaunchKernel(k, dim3(grid), dim3(MIH_BLOCK), args, 0, s);

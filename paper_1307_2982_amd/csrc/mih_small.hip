@@ -5,9 +5,9 @@
 
 namespace {
 
-// One launch for a small batch: every query is taken by G workgroups, which
-// run all its steps (Algorithm 3) on the device with no host round trip and
-// no regroup between steps.  Steps go in windows: a window is one step, or
+// One launch for a small batch: every query is taken by G workgroups (more
+// for a query with more expected work), which run all its steps (Algorithm
+// 3) on the device with no host round trip and no regroup between steps.  Steps go in windows: a window is one step, or
 // consecutive steps whose masks together fill at most one pass of the
 // query's waves.  Each workgroup takes its share of every window
 // (contiguous ranges of masks, one per wave), in step order; the workgroup
@@ -54,9 +54,9 @@ __global__ __launch_bounds__(small_waves<J>() * MIH_WAVE) void mih_small_kernel(
         binom[i / MIH_BINOM_N][i % MIH_BINOM_N] = binom_calc(i / MIH_BINOM_N, i % MIH_BINOM_N);
     __syncthreads();
     WaveStats ws = {0, 0};
-    const uint32_t G = S.groups;
-    const uint32_t q = blockIdx.x / G, g = blockIdx.x - q * G;
-    if (q < S.nq && A.qb.k[q] != 0) {
+    const uint32_t q = S.query_of[blockIdx.x];
+    const uint32_t g = blockIdx.x - S.first[q], G = S.first[q + 1] - S.first[q];
+    if (A.qb.k[q] != 0) {
         uint32_t *step_cnt = S.step_cnt + (uint64_t)q * (A.t_all + 1);
         // masks of one pass of all the query's waves: small steps run
         // together in windows of at most one pass
@@ -237,7 +237,7 @@ hipError_t mih_small(const MihArgs &A, const SmallArgs &S, hipStream_t s)
     MihArgs a = A;
     SmallArgs b = S;
     void *args[] = {&a, &b};
-    return hipLaunchKernel(k, dim3(S.nq * S.groups), dim3(small_block(A.J)), args, 0, s);
+    return hipLaunchKernel(k, dim3(S.blocks), dim3(small_block(A.J)), args, 0, s);
 }
 
 int mih_small_occupancy(uint32_t W, uint32_t tm, bool inline_codes, uint32_t J)

@@ -253,12 +253,21 @@ __device__ __forceinline__ void lookup_block(const mih::MihArgs &A, const TableD
 // step is key_base = the query's key, nbits = s_a, rho = t / m; one key
 // partition of a step (the sweep kernel) fixes the high bits of the key and
 // enumerates the rest.
-template <int W, int TM, bool INLINE, int J>
-__device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t key_base,
-                             uint32_t nbits, uint32_t rho, uint32_t rb, uint32_t re,
-                             const uint32_t (*binom)[MIH_BINOM_N], uint32_t *stage_pos,
-                             uint32_t *stage_cum, uint64_t *stage_code, WaveStats &ws)
+// Buckets a wave lists for offering in pieces (round kernel), per wave.
+constexpr uint32_t kSpillList = 64;
+
+// Returns how many huge buckets (more than A.spill_min codes; never when
+// spill_min is 0) it listed in big[] instead of walking them: the caller
+// offers them in pieces (spill_bucket).  A full list leaves the rest to
+// this wave's walk.
+template <int W, int TM, bool INLINE, int J, bool SPILL = false>
+__device__ __forceinline__ uint32_t process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t key_base,
+                                 uint32_t nbits, uint32_t rho, uint32_t rb, uint32_t re,
+                                 const uint32_t (*binom)[MIH_BINOM_N], uint32_t *stage_pos,
+                                 uint32_t *stage_cum, uint64_t *stage_code, WaveStats &ws,
+                                 uint2 *big = nullptr)
 {
+    uint32_t nbig = 0;
     const uint32_t lane = lane_id();
     const uint32_t m = A.m;
     const uint32_t rp = t / m, a = t - rp * m;
@@ -276,6 +285,19 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
         uint32_t lo[J], cnt[J];
         uint64_t head_code[J];   // HEADS: the first code of each bucket
         lookup_block<W, TM, J>(A, T, key_base, nbits, rho, r0, nmy, binom, lo, cnt, head_code);
+        // buckets of more than spill_min codes are listed, not staged
+        if (SPILL) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const uint32_t slot = nbig + lanes_below(__ballot(cnt[j] > A.spill_min));
+                const bool b = cnt[j] > A.spill_min && slot < kSpillList;
+                if (b) {
+                    big[slot] = make_uint2(lo[j], cnt[j]);
+                    cnt[j] = 0;
+                }
+                nbig += (uint32_t)__popcll(__ballot(b));
+            }
+        }
         // stage the non-empty buckets of the wave with the running count of
         // candidates before each, then walk the candidates 64 at a time
         uint32_t ne = 0, tc = 0;
@@ -375,6 +397,137 @@ __device__ void process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint
         wave_lds_sync();
         const uint32_t g_tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
         tau = g_tau < tau ? g_tau : tau;
+    }
+    return nbig;
+}
+
+// The codes at table positions [pos0, pos0 + len) of step t's table, all in
+// one bucket of query q: verified, de-duplicated and appended as in
+// process_step (the pieces of a spilled bucket).
+template <int W, bool INLINE>
+__device__ __forceinline__ void walk_range(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t pos0,
+                                           uint32_t len, WaveStats &ws)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t m = A.m;
+    const uint32_t rp = t / m, a = t - rp * m;
+    const TableDev &T = A.tables[a];
+    const bool tinl = INLINE || T.codes != nullptr;
+    uint64_t g[W];
+    (void)query_key<W>(A, q, a, g);
+    uint32_t tau = __builtin_amdgcn_readfirstlane(load_relaxed(A.qb.tau + q));
+    ws.candidates += len;
+    constexpr int kWalk = walk_depth<W>();
+    for (uint32_t e0 = 0; e0 < len; e0 += MIH_WAVE * kWalk) {
+        uint32_t id[kWalk];
+        bool live[kWalk];
+        uint64_t code[kWalk][W];
+#pragma unroll
+        for (int u = 0; u < kWalk; ++u) {
+            const uint32_t e = e0 + u * MIH_WAVE + lane;
+            live[u] = e < len;
+            id[u] = (!tinl && live[u]) ? T.ids[pos0 + e] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kWalk; ++u) {
+            const uint32_t pos = pos0 + e0 + u * MIH_WAVE + lane;
+            if (live[u]) {
+                if (tinl) load_code<W>(T.codes + (uint64_t)pos * W, code[u]);
+                else load_code<W>(A.codes + (uint64_t)id[u] * W, code[u]);
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w) code[u][w] = g[w];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kWalk; ++u) {
+            if (e0 + u * MIH_WAVE >= len) continue;   // wave-uniform
+            const uint32_t d = hamming<W>(code[u], g);
+            bool keep = live[u] && d <= tau;
+            if (keep) {
+                uint64_t x[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) x[w] = code[u][w] ^ g[w];
+                for (uint32_t j = 0; j < m; ++j) {
+                    if (j == a) continue;
+                    const uint32_t dj = table_dist<W>(x, A.tables[j]);
+                    if (j < a ? dj <= rp : dj < rp) { keep = false; break; }
+                }
+            }
+            if (keep && tinl) id[u] = T.ids[pos0 + e0 + u * MIH_WAVE + lane];
+            append_candidates(A.qb, q, keep, d, id[u]);
+            if (__ballot(keep)) tau = tighten_tau(A.qb, q, tau);
+        }
+    }
+}
+
+// Offer the bucket [lo, lo + cnt) of query q's step t in pieces, then take
+// every piece no other wave has taken.  With no room left in the round's
+// list the wave walks the bucket itself.  Nothing here waits for another
+// wave: a piece is walked by whichever wave turns its flag first.
+template <int W, bool INLINE>
+__device__ __forceinline__ void spill_bucket(const mih::MihArgs &A, uint32_t seq, uint32_t q, uint32_t t, uint32_t lo,
+                             uint32_t cnt, WaveStats &ws)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t k = (cnt + mih::kSpillPiece - 1) / mih::kSpillPiece;
+    unsigned long long e0 = 0;
+    if (lane == 0) e0 = atomicAdd(A.spill_tail, (unsigned long long)k);
+    e0 = u64_uniform<1>(__shfl(e0, 0, MIH_WAVE));
+    if (e0 + k > A.spill_cap) {
+        walk_range<W, INLINE>(A, q, t, lo, cnt, ws);
+        return;
+    }
+    for (uint32_t i = lane; i < k; i += MIH_WAVE) {
+        const uint32_t off = i * mih::kSpillPiece;
+        A.spill[e0 + i] = mih::SpillRec{q, t, lo + off, cnt - off < mih::kSpillPiece ? cnt - off : mih::kSpillPiece};
+    }
+    __threadfence();   // the pieces before their flags
+    for (uint32_t i = lane; i < k; i += MIH_WAVE)
+        __hip_atomic_store(A.spill_flag + e0 + i, 2 * seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // take back what nobody has taken, 64 entries at a time
+    for (uint32_t b = 0; b < k; b += MIH_WAVE) {
+        const bool took = b + lane < k && atomicCAS(A.spill_flag + e0 + b + lane, 2 * seq, 2 * seq + 1) == 2 * seq;
+        for (uint64_t won = __ballot(took); won; won &= won - 1) {
+            const uint32_t l = (uint32_t)__ffsll((long long)won) - 1;
+            const uint32_t off = (b + l) * mih::kSpillPiece;
+            walk_range<W, INLINE>(A, q, t, lo + off, cnt - off < mih::kSpillPiece ? cnt - off : mih::kSpillPiece, ws);
+        }
+    }
+}
+
+// Take pieces that other waves offer: batches of 64 consecutive list
+// entries through a counter, each lane testing one entry and taking it if
+// it is still offered; the wave then walks what its lanes took.  A batch
+// that reaches past the entries reserved so far ends the help (such entries,
+// and any not yet flagged, are taken by the waves that offer them, which
+// take every piece of their own that nobody has).
+template <int W, bool INLINE>
+__device__ __forceinline__ void help_spilled(const mih::MihArgs &A, uint32_t seq, WaveStats &ws)
+{
+    const uint32_t lane = lane_id();
+    for (;;) {
+        unsigned long long c0 = ~0ull, end = 0;
+        if (lane == 0) {
+            end = load_relaxed(A.spill_tail);
+            end = end < A.spill_cap ? end : A.spill_cap;
+            if (load_relaxed(A.spill_next) < end) c0 = atomicAdd(A.spill_next, (unsigned long long)MIH_WAVE);
+        }
+        c0 = u64_uniform<1>(__shfl(c0, 0, MIH_WAVE));
+        end = u64_uniform<1>(__shfl(end, 0, MIH_WAVE));
+        if (c0 >= end) return;
+        const unsigned long long i = c0 + lane;
+        bool took = false;
+        if (i < end && __hip_atomic_load(A.spill_flag + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 2 * seq)
+            took = atomicCAS(A.spill_flag + i, 2 * seq, 2 * seq + 1) == 2 * seq;
+        uint64_t won = __ballot(took);
+        if (!won) continue;
+        __threadfence();   // the pieces were written before their flags
+        for (; won; won &= won - 1) {
+            const uint32_t l = (uint32_t)__ffsll((long long)won) - 1;
+            const mih::SpillRec R = A.spill[c0 + l];
+            walk_range<W, INLINE>(A, R.slot, R.t, R.pos, R.len, ws);
+        }
     }
 }
 

@@ -137,6 +137,15 @@ def test_work_quantum_keeps_every_result(mih, setup):
         what = f"quantum {rm} chunk {chunk} look {look}"
         assert torch.equal(ids, ref_i) and torch.equal(dists, ref_d), what
         assert st["rounds"] > ref_st["rounds"], what
+    # with sweeps: steps within one quantum may run partition by partition
+    for occ, rm in [(1, 2000), (0, 2000), (1, 1 << 20)]:
+        idx.set_tuning(probes_per_lane=4, chunk=256, round_masks=rm, lookahead=16, small_batch=0,
+                       occupancy_filter=occ, sweep_shift=5, sweep_bits=16, sweep_queries=64)
+        ids, dists = idx.knn(dpool[:nq], ks)
+        what = f"quantum {rm} with sweeps, occupancy filter {occ}"
+        assert torch.equal(ids, ref_i) and torch.equal(dists, ref_d), what
+    idx.set_tuning(occupancy_filter=base["occupancy_filter"], sweep_shift=base["sweep_shift"],
+                   sweep_bits=base["sweep_bits"], sweep_queries=base["sweep_queries"])
     # serving with a quantum: every request as alone without one
     idx.set_tuning(probes_per_lane=4, chunk=256, round_masks=512, lookahead=16)
     srv = mih.Server(idx, max_queries=96, buffer_entries=96 * 3000)
