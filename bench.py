@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9",
                     help="fractions of the closed-loop capacity to replay the stream at")
-    ap.add_argument("--serve-quantum", type=int, default=1 << 20,
+    ap.add_argument("--serve-quantum", type=int, default=1 << 22,
                     help="serving leg: most shell masks a query probes per device round "
                          "(round_masks; 0: whole steps)")
     ap.add_argument("--serve-slots", type=int, default=16384)
