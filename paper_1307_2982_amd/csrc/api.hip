@@ -962,8 +962,8 @@ mih_status small_batch(mih_index *ix, const uint64_t *queries, uint32_t nq, cons
     // the uploaded block: 64-bit arrays first, then the 32-bit ones
     uint64_t up = 0;
     auto field = [&](uint64_t bytes) { const uint64_t o = up; up += (bytes + 7) / 8 * 8; return o; };
-    const uint64_t o_bo = field(8ull * nq), o_ro = field(8ull * nq), o_st = field(32), o_k = field(4ull * nq),
-                   o_cap = field(4ull * nq), o_oc = field(8), o_tau = field(4ull * nq + 64),
+    const uint64_t o_bo = field(8ull * nq), o_ro = field(8ull * nq), o_st = field(32), o_oc = field(8),
+                   o_k = field(4ull * nq), o_cap = field(4ull * nq), o_tau = field(4ull * nq + 64),
                    o_cnt = field(4ull * nq), o_hist = field(4ull * nq * nb), o_stop = field(4ull * nq),
                    o_exit = field(4ull * nq), o_sc = field(4ull * nq * nsteps);
     // workgroups per query: the device's resident workgroups shared in
@@ -1066,8 +1066,7 @@ mih_status small_batch(mih_index *ix, const uint64_t *queries, uint32_t nq, cons
     ev.end(s);
     // the statistics and the overflow count, read back together
     char *hb = h + up;
-    MIH_TRY(hipMemcpyAsync(hb, d + o_st, 32, hipMemcpyDeviceToHost, s));
-    MIH_TRY(hipMemcpyAsync(hb + 32, d + o_oc, 4, hipMemcpyDeviceToHost, s));
+    MIH_TRY(hipMemcpyAsync(hb, d + o_st, 36, hipMemcpyDeviceToHost, s));   // the overflow count follows
     MIH_TRY(hipStreamSynchronize(s));
     const unsigned long long *hs = (const unsigned long long *)hb;
     const uint32_t novf = *(const uint32_t *)(hb + 32);

@@ -44,10 +44,14 @@ constexpr uint32_t kSweepMinBits = 20;
 constexpr uint32_t kSweepXcds = 8;
 constexpr uint32_t kSweepBatch = 4;   // consecutive sweep items claimed at once
 // Device statistics slots of the engine: 0 probes, 1 candidates, 2 steps,
-// 3 appended; 4-5 the round kernel's first and last wave end (the first as
-// a complement) in the current round, 6-7 the same for the sweep kernels,
-// 8 the sum of the rounds' tails in wall-clock ticks.
-constexpr uint32_t kStatRoundEnd = 4, kStatSweepEnd = 6, kStatTail = 8, kStatSlots = 9;
+// 3 appended; from kStatRoundEnd, kTailPairs pairs (first wave end as a
+// complement, last wave end) of the round kernel in the current round, a
+// workgroup using pair blockIdx mod kTailPairs so that the atomics spread
+// over many addresses; from kStatSweepEnd the same for the sweep kernels;
+// kStatTail the sum of the rounds' tails in wall-clock ticks.
+constexpr uint32_t kTailPairs = 64;
+constexpr uint32_t kStatRoundEnd = 4, kStatSweepEnd = kStatRoundEnd + 2 * kTailPairs,
+                   kStatTail = kStatSweepEnd + 2 * kTailPairs, kStatSlots = kStatTail + 1;
 static_assert(kSweepQueries <= MIH_WAVE, "one lane per query of a sweep item");
 // Partition kernel: the largest partition (key bits) whose occupancy bits
 // are staged in LDS (2^18 bits = 32 KiB).

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
     const uint32_t n_groups = A.ctrl->n_groups;
     const uint64_t total = A.ctrl->total_items;
     const uint32_t chunk = A.chunk;
-    const uint32_t seq = A.ctrl->seq;
+    const uint32_t seq = SPILL ? A.ctrl->seq : 0u;
     WaveStats ws = {0, 0};
     bool worked = false;
     for (;;) {
@@ -123,10 +123,10 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_round_kernel(mih::MihArgs A)
             }
         }
     }
-    if (worked && lane == 0) record_end(A.stats + mih::kStatRoundEnd);   // out of work items
     // out of work items: take what is offered now, then leave (waiting for
     // more would put device-scope polls of many waves on the path of the
     // atomics of the waves still searching)
+    if (lane == 0 && worked) record_end(A.stats + mih::kStatRoundEnd);
     if (SPILL) help_spilled<W, INLINE>(A, seq, ws);
     if (lane == 0) {
         atomicAdd(&A.stats[0], (unsigned long long)ws.probes);
@@ -818,7 +818,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_part_kernel(mih::MihArgs A)
 __global__ __launch_bounds__(MIH_BLOCK) void mih_advance_kernel(mih::MihArgs A)
 {
     const uint32_t i = blockIdx.x * MIH_BLOCK + threadIdx.x;
-    if (i == 0) fold_tails(A.stats);
+    if (i < MIH_WAVE) fold_tails(A.stats);   // the first wave
     if (i >= A.ctrl->n_active) return;
     const uint32_t q = A.active[i];
     const uint32_t nb = A.qb.bits + 1;

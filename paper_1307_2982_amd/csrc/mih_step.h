@@ -62,24 +62,39 @@ __device__ __forceinline__ uint64_t u64_uniform(uint64_t x)
 // Round tail: each wave (round kernel) or workgroup (sweep kernels) that
 // took work records when it ran out of it, as the largest end time and the
 // largest complement of an end time (so that zero-filled slots start both
-// maxima), in the constant-rate wall clock.  The advance kernel adds each
-// launch's spread (last end minus first end) to a running sum and clears
-// the slots for the next round.
-__device__ __forceinline__ void record_end(unsigned long long *slot)
+// maxima), in the constant-rate wall clock, in the slot pair of its
+// workgroup.  The advance kernel's first wave adds each launch's spread
+// (last end minus first end over the pairs) to a running sum and clears the
+// pairs for the next round.
+__device__ __forceinline__ void record_end(unsigned long long *pairs)
 {
+    unsigned long long *slot = pairs + 2 * (blockIdx.x % mih::kTailPairs);
     const unsigned long long now = (unsigned long long)__builtin_amdgcn_s_memrealtime();
     atomicMax(slot, ~now);
     atomicMax(slot + 1, now);
 }
 
+// Called by one whole wave.
 __device__ __forceinline__ void fold_tails(unsigned long long *stats)
 {
-    for (uint32_t k = mih::kStatRoundEnd; k <= mih::kStatSweepEnd; k += 2) {
-        const unsigned long long last = stats[k + 1];
-        if (last) stats[mih::kStatTail] += last - ~stats[k];
-        stats[k] = 0;
-        stats[k + 1] = 0;
+    static_assert(mih::kTailPairs == MIH_WAVE, "one pair per lane");
+    const uint32_t lane = lane_id();
+    unsigned long long add = 0;
+    for (uint32_t k = mih::kStatRoundEnd; k <= mih::kStatSweepEnd; k += 2 * mih::kTailPairs) {
+        const unsigned long long first_c = stats[k + 2 * lane], last = stats[k + 2 * lane + 1];
+        unsigned long long mx = last, mc = last ? first_c : 0ull;   // max end; max complement = min end
+#pragma unroll
+        for (int sh = 1; sh < MIH_WAVE; sh <<= 1) {
+            const unsigned long long o1 = (unsigned long long)__shfl_xor((long long)mx, sh, MIH_WAVE);
+            const unsigned long long o2 = (unsigned long long)__shfl_xor((long long)mc, sh, MIH_WAVE);
+            mx = o1 > mx ? o1 : mx;
+            mc = o2 > mc ? o2 : mc;
+        }
+        if (mx) add += mx - ~mc;
+        stats[k + 2 * lane] = 0;
+        stats[k + 2 * lane + 1] = 0;
     }
+    if (lane == 0) stats[mih::kStatTail] += add;
 }
 
 struct WaveStats {
@@ -261,7 +276,7 @@ constexpr uint32_t kSpillList = 64;
 // offers them in pieces (spill_bucket).  A full list leaves the rest to
 // this wave's walk.
 template <int W, int TM, bool INLINE, int J, bool SPILL = false>
-__device__ __forceinline__ uint32_t process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t key_base,
+__device__ uint32_t process_step(const mih::MihArgs &A, uint32_t q, uint32_t t, uint32_t key_base,
                                  uint32_t nbits, uint32_t rho, uint32_t rb, uint32_t re,
                                  const uint32_t (*binom)[MIH_BINOM_N], uint32_t *stage_pos,
                                  uint32_t *stage_cum, uint64_t *stage_code, WaveStats &ws,
