@@ -41,8 +41,9 @@ inline uint32_t search_capacity(uint32_t k, uint32_t mult)
 // stays at the radius.
 constexpr uint32_t kRnnK = 0xFFFFFFFFu;
 // First candidate-buffer capacity of an r-neighbour query (entries); a query
-// with more hits is re-run with the exact count.
-constexpr uint32_t kRnnCapacity = 1024;
+// with more hits is re-run with the exact count.  (1024 re-ran every query
+// of 1e8 x 64-bit at the median 1000th distance, ~1,200 hits each.)
+constexpr uint32_t kRnnCapacity = 4096;
 
 class Engine;
 
