@@ -486,7 +486,7 @@ struct PartLds {
     uint32_t qtau[MIH_WAVE];         // bound of the query (refreshed after appends)
     uint64_t qg[MIH_WAVE][W];        // the query's words
     uint32_t queue[kQueue];          // occupied buckets: low key bits << 6 | wave query
-    uint16_t pend[2 * MIH_WAVE];     // group indices of queries with masks in the partition
+    uint16_t pend[2 * MIH_WAVE];     // queries with masks in the partition (index in the work item)
 };
 
 // Verify candidate `code` (table position pos) of query k of the wave:
@@ -606,8 +606,8 @@ __device__ void part_tighten(const mih::MihArgs &A, PartLds<W, J> &S, uint64_t t
     wave_lds_sync();
 }
 
-// The queries S.pend[0 .. nq) (at most 64; indices in the group at step t
-// whose active entries start at slot_start) against partition h of L key
+// The queries S.pend[0 .. nq) (at most 64; indices among the active entries
+// that start at slot_start: the work item's queries) against partition h of L key
 // bits, whose occupancy bits are in `occ` (bit v of the partition: word
 // v / 32).
 template <int W, int TM, bool INLINE, int J>
@@ -787,11 +787,11 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_part_kernel(mih::MihArgs A)
                     meets = wgt <= rp && rp - wgt <= L;
                 }
                 const uint64_t bal = __ballot(meets);
-                if (meets) P.pend[npend + lanes_below(bal)] = (uint16_t)(q0 + s0 + lane);
+                if (meets) P.pend[npend + lanes_below(bal)] = (uint16_t)(s0 + lane);   // < sweep_q <= 4096
                 npend += (uint32_t)__popcll(bal);
                 if (npend >= MIH_WAVE) {
                     wave_lds_sync();
-                    part_queries<W, TM, INLINE, J>(A, gt, gslot, L, h, MIH_WAVE, occ, binom, P, ws);
+                    part_queries<W, TM, INLINE, J>(A, gt, gslot + q0, L, h, MIH_WAVE, occ, binom, P, ws);
                     npend -= MIH_WAVE;
                     if (lane < npend) P.pend[lane] = P.pend[MIH_WAVE + lane];
                     wave_lds_sync();
@@ -799,7 +799,7 @@ __global__ __launch_bounds__(MIH_BLOCK) void mih_part_kernel(mih::MihArgs A)
             }
             if (npend) {
                 wave_lds_sync();
-                part_queries<W, TM, INLINE, J>(A, gt, gslot, L, h, npend, occ, binom, P, ws);
+                part_queries<W, TM, INLINE, J>(A, gt, gslot + q0, L, h, npend, occ, binom, P, ws);
             }
         }
     }

@@ -251,3 +251,24 @@ def test_mih_matches_linscan_mixed_k(mih):
     gi = np.concatenate([as_u32(ids)[off[i]:off[i + 1]] for i in sel])
     gd = np.concatenate([as_u32(dists)[off[i]:off[i + 1]] for i in sel])
     assert np.array_equal(gi, oi) and np.array_equal(gd, od)
+
+
+def test_partition_sweep_of_a_group_larger_than_65536_queries(mih):
+    # a swept step of more than 65,536 queries at once: the partition
+    # kernel's work items index their queries within the item
+    import torch
+    n, nq = 300_007, 70_000
+    codes = datagen.uniform_codes(n, 64, 961)
+    queries = datagen.uniform_codes(nq, 64, 962)
+    dc, dq = to_dev(codes), to_dev(queries)
+    idx = mih.build(dc, 3, table_mode="heads", codes_mode="inline")
+    idx.set_tuning(probes_per_lane=4, chunk=256, occupancy_filter=1, sweep_shift=6, sweep_bits=16,
+                   sweep_queries=4096, small_batch=0)
+    ids, dists, st = idx.knn(dq, 3, stats=True)
+    li, ld = mih.linscan_knn(dc, dq, 3)
+    assert torch.equal(ids, li) and torch.equal(dists, ld)
+    sel = np.arange(nq - 300, nq)
+    oi, od = oracle.knn(codes, queries[sel], 3)
+    assert_same(ids.reshape(nq, 3)[sel[0]:].reshape(-1), dists.reshape(nq, 3)[sel[0]:].reshape(-1), oi, od,
+                "last queries of the group")
+    idx.close()
