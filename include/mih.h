@@ -107,6 +107,18 @@ typedef struct mih_build_opts {
                                     retained after the call. */
     uint32_t inline_tables;      /* MIXED: INLINE tables, 1 <= inline_tables < m
                                     (ignored by the other modes) */
+    const char *autotune_cache;  /* path of a file of autotuned launches, or
+                                    NULL.  mih_autotune on this index first
+                                    looks up the index's shape and the sample
+                                    (n, bits, m, table and codes modes, inline
+                                    tables, number of queries, k) there and, if
+                                    found, takes that tuning without timing;
+                                    otherwise it times its grid and stores the
+                                    result.  The file is one JSON object, key:
+                                    [the mih_tuning fields in order]; it is
+                                    rewritten whole on a store, and a missing
+                                    or unreadable file counts as empty (a store
+                                    that fails is skipped).  Copied at build. */
 } mih_build_opts;
 
 typedef struct mih_index mih_index;   /* opaque, owned by the library */

@@ -37,7 +37,7 @@ class MihError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("table_mode", ctypes.c_int), ("codes_mode", ctypes.c_int),
                 ("mem_budget_bytes", ctypes.c_uint64), ("bit_order", ctypes.c_void_p),
-                ("inline_tables", ctypes.c_uint32)]
+                ("inline_tables", ctypes.c_uint32), ("autotune_cache", ctypes.c_char_p)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -46,7 +46,7 @@ class IndexInfo(ctypes.Structure):
                 ("sub_len", ctypes.c_uint32 * 64), ("sub_start", ctypes.c_uint32 * 64),
                 ("dir_bits", ctypes.c_uint32 * 64), ("device_bytes", ctypes.c_uint64),
                 ("build_ms", ctypes.c_double), ("bit_order", ctypes.c_uint16 * 256),
-                ("inline_tables", ctypes.c_uint32)]
+                ("inline_tables", ctypes.c_uint32), ("autotune_cache", ctypes.c_char_p)]
 
 
 class TableView(ctypes.Structure):
@@ -387,10 +387,12 @@ class Index:
 
 
 def build(codes: torch.Tensor, m: int, table_mode: str = "auto", codes_mode: str = "auto",
-          mem_budget_bytes: int = 0, bit_order=None, inline_tables: int = 0) -> Index:
+          mem_budget_bytes: int = 0, bit_order=None, inline_tables: int = 0,
+          autotune_cache: str | None = None) -> Index:
     """Build the m substring tables (Algorithm 1) on the device; bit_order
     (a permutation of the code bits, Section 5.5) places the substrings;
-    codes_mode "mixed" keeps inline codes in the first inline_tables tables."""
+    codes_mode "mixed" keeps inline codes in the first inline_tables tables;
+    autotune_cache: a file where autotune() keeps and looks up its results."""
     codes = _codes_arg(codes, "codes")
     n, W = codes.shape
     order = None
@@ -399,7 +401,8 @@ def build(codes: torch.Tensor, m: int, table_mode: str = "auto", codes_mode: str
             raise ValueError("bit_order must list every code bit once")
         order = (ctypes.c_uint16 * (64 * W))(*[int(b) for b in bit_order])
     opts = BuildOpts(TABLE_MODES[table_mode], CODES_MODES[codes_mode], mem_budget_bytes,
-                     ctypes.cast(order, ctypes.c_void_p) if order is not None else None, inline_tables)
+                     ctypes.cast(order, ctypes.c_void_p) if order is not None else None, inline_tables,
+                     autotune_cache.encode() if autotune_cache else None)
     h = ctypes.c_void_p()
     rc = load().mih_build(codes.data_ptr() if n else None, n, 64 * W, m, ctypes.byref(opts),
                           _stream(), ctypes.byref(h))

@@ -6,7 +6,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "engine.h"
@@ -663,7 +665,7 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     if (!bits_ok(bits) || m < 1 || m > MIH_M_MAX || m > bits) return MIH_ERR_INVALID;
     if ((bits + m - 1) / m > MIH_SUBSTRING_MAX) return MIH_ERR_UNSUPPORTED;
     if (n > 0xFFFFFFFEull || (n && !codes) || ((uintptr_t)codes & 7) != 0) return MIH_ERR_INVALID;
-    mih_build_opts o = {MIH_TABLE_AUTO, MIH_CODES_AUTO, 0, nullptr, 0};
+    mih_build_opts o = {MIH_TABLE_AUTO, MIH_CODES_AUTO, 0, nullptr, 0, nullptr};
     if (opts) o = *opts;
     if (o.bit_order) {
         // a permutation of 0 .. bits-1
@@ -685,6 +687,7 @@ mih_status mih_build(const uint64_t *codes, uint64_t n, uint32_t bits, uint32_t 
     mih_index *ix = new (std::nothrow) mih_index();
     if (!ix) return MIH_ERR_NOMEM;
     (void)hipGetDevice(&ix->device);
+    if (o.autotune_cache) ix->autotune_cache = o.autotune_cache;
     ix->codes = codes;
     ix->n = n;
     ix->bits = bits;
@@ -1454,6 +1457,85 @@ void mih_server_destroy(mih_server *srv) { delete srv; }
 
 // ============================================================== autotuner
 
+namespace {
+
+constexpr int kTuningFields = sizeof(mih_tuning) / sizeof(uint32_t);
+static_assert(sizeof(mih_tuning) == kTuningFields * sizeof(uint32_t), "mih_tuning holds uint32_t fields only");
+
+// The key of an autotuned launch: the index's shape and the sample (one k,
+// or a hash of the per-query k values).
+std::string autotune_key(const mih_index *ix, uint32_t nq, const std::vector<uint32_t> &kv)
+{
+    bool one = true;
+    uint64_t h = 1469598103934665603ull;   // FNV-1a over the k values
+    for (uint32_t v : kv) {
+        one &= v == kv[0];
+        for (int b = 0; b < 4; ++b) { h ^= (v >> (8 * b)) & 0xFFu; h *= 1099511628211ull; }
+    }
+    char buf[256];
+    if (one)
+        std::snprintf(buf, sizeof buf, "n=%llu bits=%u m=%u table=%u codes=%u inline=%u queries=%u k=%u",
+                      (unsigned long long)ix->n, ix->bits, ix->m, ix->table_mode, ix->codes_mode, ix->inline_tables,
+                      nq, kv.empty() ? 0u : kv[0]);
+    else
+        std::snprintf(buf, sizeof buf, "n=%llu bits=%u m=%u table=%u codes=%u inline=%u queries=%u k=%016llx",
+                      (unsigned long long)ix->n, ix->bits, ix->m, ix->table_mode, ix->codes_mode, ix->inline_tables,
+                      nq, (unsigned long long)h);
+    return buf;
+}
+
+// Entries of a cache file: lines of the form  "key": [f0, f1, ...]  (the
+// other lines, braces included, carry nothing).  Entries whose field count
+// is not that of mih_tuning are dropped.
+std::map<std::string, std::vector<uint32_t>> read_autotune_cache(const std::string &path)
+{
+    std::map<std::string, std::vector<uint32_t>> out;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return out;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        const char *q0 = std::strchr(line, '"');
+        const char *q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+        const char *b0 = q1 ? std::strchr(q1, '[') : nullptr;
+        if (!b0) continue;
+        std::vector<uint32_t> v;
+        const char *p = b0 + 1;
+        while (*p && *p != ']') {
+            char *end = nullptr;
+            const unsigned long x = std::strtoul(p, &end, 10);
+            if (end == p) { ++p; continue; }
+            v.push_back((uint32_t)x);
+            p = end;
+        }
+        if ((int)v.size() == kTuningFields) out[std::string(q0 + 1, q1)] = v;
+    }
+    std::fclose(f);
+    return out;
+}
+
+void store_autotune_cache(const std::string &path, const std::string &key, const mih_tuning &t)
+{
+    auto entries = read_autotune_cache(path);
+    const uint32_t *f = reinterpret_cast<const uint32_t *>(&t);
+    entries[key] = std::vector<uint32_t>(f, f + kTuningFields);
+    const std::string tmp = path + ".tmp";
+    FILE *o = std::fopen(tmp.c_str(), "w");
+    if (!o) return;
+    std::fprintf(o, "{\n");
+    size_t i = 0;
+    for (const auto &e : entries) {
+        std::fprintf(o, "  \"%s\": [", e.first.c_str());
+        for (int j = 0; j < kTuningFields; ++j) std::fprintf(o, j ? ", %u" : "%u", e.second[j]);
+        std::fprintf(o, "]%s\n", ++i < entries.size() ? "," : "");
+    }
+    std::fprintf(o, "}\n");
+    const bool ok = std::fclose(o) == 0;
+    if (ok) (void)std::rename(tmp.c_str(), path.c_str());
+    else (void)std::remove(tmp.c_str());
+}
+
+}  // namespace
+
 extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint32_t nq, uint32_t k,
                                    const uint32_t *k_per_query, void *stream, mih_tuning *chosen)
 {
@@ -1465,6 +1547,20 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
     hipStream_t s = (hipStream_t)stream;
     std::vector<uint32_t> kv;
     MIH_TRY_STATUS(read_k(nq, k, k_per_query, s, kv));
+    // a launch tuned before for the same index shape and sample
+    const std::string key = idx->autotune_cache.empty() ? std::string() : autotune_key(idx, nq, kv);
+    if (!key.empty()) {
+        const auto entries = read_autotune_cache(idx->autotune_cache);
+        const auto it = entries.find(key);
+        if (it != entries.end()) {
+            mih_tuning t;
+            std::memcpy(&t, it->second.data(), sizeof t);
+            if (mih_set_tuning(idx, &t) == MIH_OK) {
+                if (chosen) *chosen = t;
+                return MIH_OK;
+            }
+        }
+    }
     uint64_t total = 0;
     for (uint32_t v : kv) total += v;
     Scratch out;
@@ -1582,5 +1678,6 @@ extern "C" mih_status mih_autotune(mih_index *idx, const uint64_t *queries, uint
     out.release();
     if (st != MIH_OK) return st;
     if (chosen) *chosen = best;
+    if (st2 == MIH_OK && !key.empty()) store_autotune_cache(idx->autotune_cache, key, best);
     return st2;
 }

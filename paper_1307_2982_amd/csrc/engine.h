@@ -6,6 +6,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <unordered_map>
 #include <vector>
 
@@ -55,6 +56,7 @@ void index_args(const mih_index *ix, MihArgs &A);
 
 struct mih_index {
     int device = 0;
+    std::string autotune_cache;   // file of autotuned launches ("" for none)
     const uint64_t *codes = nullptr;
     uint64_t n = 0;
     uint32_t bits = 0, W = 0, m = 0;
